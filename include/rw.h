@@ -1,0 +1,244 @@
+/* rw.h — C ABI of the MI355X random-walker solver (librw.so).
+ *
+ * Problem (random-walker segmentation, the operator the paper lists in
+ * Sec. III-A and benchmarks hierarchically in Sec. IV-B, Table III):
+ *   6-connected voxel grid, Gaussian edge weights
+ *       w_ij = exp(-beta (g_i - g_j)^2) + w_eps,
+ *   g = (v - norm_lo) / (norm_hi - norm_lo) the normalised intensity;
+ *   L = D - W; seeded voxels M carry Dirichlet data m^s = [label == s];
+ *   every label s solves L_U x^s = -B^T m^s on the unseeded voxels U by
+ *   Jacobi-preconditioned conjugate gradients, stopped when
+ *   ||r|| <= tol ||b||.  Edges never leave the volume.
+ *
+ * Layout: every grid is C order [nz][ny][nx], x fastest; multi-grid arrays
+ * are planar, [count][nz][ny][nx].  Labels: uint8, 0 = unseeded, 1..K = seed
+ * label, label 1 = background.
+ *
+ * Ownership: every data pointer is caller-owned DEVICE memory unless marked
+ * "host".  The library never allocates device memory for data: scratch comes
+ * from the caller's workspace (rw_*_workspace_bytes).  A context owns only a
+ * private HIP stream, events, a small pinned host buffer for convergence
+ * polling, and cached graph executables.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ * default stream).  Work runs on the context's stream, ordered after all work
+ * already queued on `stream`, and `stream` is made to wait for it.  Calls that
+ * poll convergence return after their device work is complete.  Calls on one
+ * context must not overlap (one host thread per context).
+ *
+ * Errors: negative statuses are failures, detected before any output is
+ * written unless stated; RW_NOT_CONVERGED (positive) means the last iterate
+ * was written.  rw_last_error() gives a per-thread message.
+ */
+#ifndef RW_H_
+#define RW_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RW_MAX_LABELS 16
+
+typedef enum {
+    RW_OK = 0,
+    RW_NOT_CONVERGED = 1,     /* max_iter reached: last iterate written, stats valid */
+    RW_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad option, label > K */
+    RW_ERR_NO_SEEDS = -2,     /* no seed at all, or a solved label has no seed */
+    RW_ERR_SINGULAR = -3,     /* an unseeded voxel has zero degree (all weights 0) */
+    RW_ERR_BREAKDOWN = -4,    /* CG breakdown: p.Ap <= 0 or not finite */
+    RW_ERR_NONFINITE = -5,    /* NaN/Inf in the input or in the weights */
+    RW_ERR_WORKSPACE = -6,    /* workspace missing or smaller than required */
+    RW_ERR_HIP = -7,          /* a HIP runtime call failed (see rw_last_error) */
+    RW_ERR_UNSUPPORTED = -8   /* combination of options not implemented */
+} rw_status;
+
+typedef enum { RW_DT_U16 = 1, RW_DT_F32 = 2, RW_DT_F64 = 3 } rw_dtype;
+
+typedef enum {
+    RW_PREC_FP64 = 0,  /* float64 weights, vectors and reductions */
+    RW_PREC_MIXED = 1  /* float32 weights and vectors, float64 dot products,
+                          float64 residual + iterative refinement */
+} rw_precision;
+
+typedef struct {
+    int64_t nx, ny, nz;
+} rw_dims;
+
+/* Input volume.  g = (v - norm_lo) / (norm_hi - norm_lo); norm_hi <= norm_lo
+ * means a constant image (g = 0, all weights 1 + w_eps). */
+typedef struct {
+    const void* data; /* device, [nz][ny][nx] of `dtype` */
+    int32_t dtype;    /* rw_dtype */
+    rw_dims dims;
+    double norm_lo, norm_hi;
+} rw_volume;
+
+typedef struct {
+    const uint8_t* labels; /* device, [nz][ny][nx]; 0 = unseeded, 1..num_labels */
+    int32_t num_labels;    /* K, 1 <= K <= RW_MAX_LABELS */
+} rw_seeds;
+
+typedef struct {
+    double beta;          /* >= 0 */
+    double w_eps;         /* added to every weight; >= 0 in normal use */
+    double tol;           /* relative residual, > 0 (1e-6) */
+    double inner_tol;     /* mixed: relative tolerance of refinement steps after
+                             the first (1e-3); the first inner solve uses tol */
+    int32_t max_iter;     /* CG iterations per solve (20000) */
+    int32_t max_refine;   /* mixed: refinement steps (5) */
+    int32_t precision;    /* rw_precision */
+    int32_t solve_all_labels; /* 0: solve labels 2..K, background = 1 - sum;
+                                 1: solve all K labels independently */
+    int32_t check_interval;   /* CG iterations between convergence polls (even, 16) */
+    int32_t use_graph;        /* 1: replay each poll interval as a HIP graph */
+    int32_t kernel_timing;    /* 1: time every CG pass with events (no graph) */
+    int32_t reserved;
+    const void* x0;       /* device, initial guess [R][nz][ny][nx] float64 for the
+                             solved labels (read on unseeded voxels), or NULL = 0 */
+} rw_options;
+
+/* Statistics of one call (host memory). */
+typedef struct {
+    int32_t iters[RW_MAX_LABELS];        /* CG iterations per solved label (summed over
+                                            refinement steps) */
+    int32_t label_status[RW_MAX_LABELS]; /* per solved label: rw_status */
+    double rel_residual[RW_MAX_LABELS];  /* final true float64 ||b - Ax|| / ||b|| */
+    int32_t num_solved;                  /* R */
+    int32_t refinements;                 /* mixed: residual evaluations after the first */
+    double device_ms;                    /* whole call on the device (events) */
+    double loop_ms;                      /* CG iteration loops only */
+    /* kernel_timing = 1: summed durations of the CG passes over the iterations
+       in which at least one label was still iterating, their launch count,
+       and sum over those iterations of the number of labels iterating */
+    double pass_ms[2];
+    int64_t pass_launches[2];
+    int64_t rhs_iterations;
+    int64_t active_bricks;               /* brick solves: bricks solved */
+    int64_t unknowns;                    /* unseeded voxels solved for */
+} rw_stats;
+
+/* Fine-level brick: origin and size in voxels of the fine grid. */
+typedef struct {
+    int32_t ox, oy, oz, sx, sy, sz;
+} rw_brick;
+
+typedef struct rw_context rw_context;
+
+/* Context: creates a private stream on the current device. */
+rw_status rw_context_create(rw_context** out);
+void rw_context_destroy(rw_context* ctx);
+
+const char* rw_status_string(rw_status s);
+const char* rw_last_error(void);
+void rw_default_options(rw_options* opts);
+
+/* Normalisation range (min, max) of a volume, computed on the device.
+ * lo_hi: host, 2 doubles.  NaN in the volume -> RW_ERR_NONFINITE. */
+rw_status rw_minmax(rw_context* ctx, const rw_volume* vol, double* lo_hi, void* stream);
+
+/* Materialised edge weights and Jacobi inverse diagonal.
+ * w_out: [3][nz][ny][nx] (float64 for RW_PREC_FP64, float32 for MIXED);
+ *   w_out[a][v] is the weight of edge (v, v + e_a), a = 0 (x), 1 (y), 2 (z);
+ *   the last plane along each axis is 0 (no edge).
+ * dinv_out: NULL or [nz][ny][nx] of the same type: 1 / sum of the (up to six)
+ *   weights at v when v is unseeded, 0 on seeds (seeds must then be given). */
+rw_status rw_build_weights(rw_context* ctx, const rw_volume* vol, double beta, double w_eps,
+                           int32_t precision, void* w_out, void* dinv_out,
+                           const rw_seeds* seeds_or_null, void* stream);
+
+/* The operator q = L_U p of the Dirichlet system, matrix free, weights
+ * recomputed from the volume (the CG kernel's own stencil).  p: [nz][ny][nx]
+ * float64 (FP64) or float32 (MIXED), must be 0 on seeded voxels; q_out: same
+ * type and shape, meaningful on unseeded voxels.  ws: workspace of
+ * rw_operator_workspace_bytes. */
+size_t rw_operator_workspace_bytes(rw_dims dims, int32_t precision);
+rw_status rw_apply_operator(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                            double beta, double w_eps, int32_t precision, const void* p,
+                            void* q_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Whole-volume solve.
+ * prob_out: [K][nz][ny][nx], float64 for RW_PREC_FP64, float32 for MIXED;
+ *   seeds exact; with solve_all_labels = 0 label 1 is 1 - sum of the others.
+ * argmax_out: NULL or uint8 [nz][ny][nx], 1-based label of the largest
+ *   probability, lowest label on ties.
+ * ws: workspace of rw_solve_workspace_bytes(dims, K, precision, solve_all).
+ * stats: host, may be NULL. */
+size_t rw_solve_workspace_bytes(rw_dims dims, int32_t num_labels, int32_t precision,
+                                int32_t solve_all_labels);
+rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                   const rw_options* opts, void* prob_out, uint8_t* argmax_out, void* ws,
+                   size_t ws_bytes, rw_stats* stats, void* stream);
+
+/* One LOD step: g_out[c] = mean of the (up to) 2x2x2 fine values of g
+ * (normalised float32 of the input volume for level 0, else the previous
+ * level's float32); coarse size ceil(n/2).  seeds_out (optional): coarse label
+ * map, label s iff the block holds seeds of s only (conflicts -> 0). */
+rw_status rw_downsample(rw_context* ctx, const rw_volume* fine, const uint8_t* fine_labels,
+                        float* g_out, uint8_t* labels_out, void* stream);
+
+/* Brick activity on the fine grid from coarse probabilities.
+ * coarse_prob: [K][coarse dims] float32; upsampling factor f (fine index i
+ *   <-> coarse coordinate (i + 0.5)/f - 0.5, clamped, trilinear).
+ * The fine grid is tiled into bricks of brick_size with the first cut at
+ *   grid_offset (0 = none) per axis; a brick is active iff a voxel of the brick
+ *   or of its face shell has lo_thr < p_s < hi_thr for some label, or a seed
+ *   in the brick differs from the upsampled argmax.
+ * bricks_out: host, capacity >= number of candidate bricks (n_candidates);
+ *   receives the active bricks, sorted by decreasing voxel count, ties by
+ *   position.  n_active: host. */
+rw_status rw_classify_bricks(rw_context* ctx, const float* coarse_prob, rw_dims coarse_dims,
+                             int32_t num_labels, int32_t factor, const uint8_t* fine_labels,
+                             rw_dims fine_dims, const int32_t brick_size[3],
+                             const int32_t grid_offset[3], double lo_thr, double hi_thr,
+                             rw_brick* bricks_out, int32_t capacity, int32_t* n_candidates,
+                             int32_t* n_active, void* stream);
+
+/* Batched solve of many bricks of the fine level in one persistent launch.
+ * Each brick solves the random walker restricted to the brick: unknowns are
+ * its unseeded voxels; Dirichlet data are its seeds and every in-volume face
+ * neighbour outside it (seed value if seeded, else the upsampled coarse
+ * probability).  x0 = the upsampled coarse probabilities; stopping
+ * ||r|| <= tol ||b|| per brick and label.  Precision MIXED (float32 CG,
+ * float64 dots) or FP64.
+ * bricks: host array of n_bricks.  prob_out: [K][nz][ny][nx] float32 fine
+ *   grid: brick voxels are overwritten; other voxels untouched.
+ * brick_iters: NULL or host int32 [n_bricks][R] iterations per brick/label.
+ * ws: rw_bricks_workspace_bytes(...). */
+size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32_t num_labels,
+                                 int32_t precision, int32_t solve_all_labels);
+rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* fine_seeds,
+                          const float* coarse_prob, rw_dims coarse_dims, int32_t factor,
+                          const rw_brick* bricks, int32_t n_bricks, const rw_options* opts,
+                          float* prob_out, int32_t* brick_iters, void* ws, size_t ws_bytes,
+                          rw_stats* stats, void* stream);
+
+/* Upsampled coarse probabilities written into the fine grid for every
+ * voxel of the listed bricks (the inactive bricks), seeds exact. */
+rw_status rw_fill_bricks(rw_context* ctx, const float* coarse_prob, rw_dims coarse_dims,
+                         int32_t num_labels, int32_t factor, const uint8_t* fine_labels,
+                         rw_dims fine_dims, const rw_brick* bricks, int32_t n_bricks,
+                         float* prob_out, void* stream);
+
+/* Adjoint gradient of a loss L(x^s) of one solved label s (float64).
+ * x_full: [nz][ny][nx] the forward solution of label s (seeds exact).
+ * grad_x: [nz][ny][nx] dL/dx (read on unseeded voxels).
+ * Solves L_U lam = dL/dx_U with the forward operator (symmetric), then
+ *   c_e = (lam_i - lam_j)(x_i - x_j) w_e,
+ *   dL/dbeta = sum_e c_e (g_i - g_j)^2,
+ *   dL/dg_i  = sum_{e=(i,j)} 2 beta c_e (g_i - g_j)   (g normalised).
+ * grad_g_out: NULL or [nz][ny][nx] float64; grad_beta_out: NULL or host double.
+ * ws: rw_backward_workspace_bytes. */
+size_t rw_backward_workspace_bytes(rw_dims dims);
+rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                            const rw_options* opts, int32_t label, const double* x_full,
+                            const double* grad_x, double* grad_g_out, double* grad_beta_out,
+                            void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RW_H_ */

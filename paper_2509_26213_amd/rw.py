@@ -1,0 +1,336 @@
+"""Python binding of librw.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/rw.h; all
+arithmetic runs in the library's HIP kernels.  Tensors must live on the GPU;
+the current torch stream is passed as the call's stream.  If the library is
+missing the import of ``lib()`` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librw.so")
+
+RW_MAX_LABELS = 16
+RW_OK = 0
+RW_NOT_CONVERGED = 1
+RW_ERR_INVALID_ARG = -1
+RW_ERR_NO_SEEDS = -2
+RW_ERR_SINGULAR = -3
+RW_ERR_BREAKDOWN = -4
+RW_ERR_NONFINITE = -5
+RW_ERR_WORKSPACE = -6
+RW_ERR_HIP = -7
+RW_ERR_UNSUPPORTED = -8
+
+RW_DT_U16, RW_DT_F32, RW_DT_F64 = 1, 2, 3
+PREC = {"fp64": 0, "mixed": 1}
+
+# every symbol include/rw.h declares
+EXPORTS = [
+    "rw_context_create", "rw_context_destroy", "rw_status_string", "rw_last_error",
+    "rw_default_options", "rw_minmax", "rw_build_weights", "rw_operator_workspace_bytes",
+    "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
+    "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
+    "rw_backward_workspace_bytes", "rw_solve_backward",
+]
+
+
+class RWError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"{detail} (status {status})")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Volume(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("dims", Dims),
+                ("norm_lo", ctypes.c_double), ("norm_hi", ctypes.c_double)]
+
+
+class Seeds(ctypes.Structure):
+    _fields_ = [("labels", ctypes.c_void_p), ("num_labels", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("w_eps", ctypes.c_double), ("tol", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("solve_all_labels", ctypes.c_int32), ("check_interval", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("kernel_timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("x0", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32 * RW_MAX_LABELS),
+                ("label_status", ctypes.c_int32 * RW_MAX_LABELS),
+                ("rel_residual", ctypes.c_double * RW_MAX_LABELS),
+                ("num_solved", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("device_ms", ctypes.c_double), ("loop_ms", ctypes.c_double),
+                ("pass_ms", ctypes.c_double * 2), ("pass_launches", ctypes.c_int64 * 2),
+                ("rhs_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
+                ("unknowns", ctypes.c_int64)]
+
+    def to_dict(self):
+        R = self.num_solved
+        return dict(iters=list(self.iters[:R]), label_status=list(self.label_status[:R]),
+                    rel_residual=list(self.rel_residual[:R]), num_solved=R,
+                    refinements=self.refinements, device_ms=self.device_ms,
+                    loop_ms=self.loop_ms, pass_ms=list(self.pass_ms),
+                    pass_launches=list(self.pass_launches), rhs_iterations=self.rhs_iterations,
+                    active_bricks=self.active_bricks, unknowns=self.unknowns)
+
+
+class Brick(ctypes.Structure):
+    _fields_ = [("ox", ctypes.c_int32), ("oy", ctypes.c_int32), ("oz", ctypes.c_int32),
+                ("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("sz", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librw.so; raises if it was not built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run python -m paper_2509_26213_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    L.rw_context_create.argtypes = [ctypes.POINTER(P)]
+    L.rw_context_destroy.argtypes = [P]
+    L.rw_context_destroy.restype = None
+    L.rw_status_string.argtypes = [I32]
+    L.rw_status_string.restype = ctypes.c_char_p
+    L.rw_last_error.restype = ctypes.c_char_p
+    L.rw_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.rw_default_options.restype = None
+    L.rw_minmax.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(D), P]
+    L.rw_build_weights.argtypes = [P, ctypes.POINTER(Volume), D, D, I32, P, P,
+                                   ctypes.POINTER(Seeds), P]
+    L.rw_operator_workspace_bytes.argtypes = [Dims, I32]
+    L.rw_operator_workspace_bytes.restype = SZ
+    L.rw_apply_operator.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), D, D, I32,
+                                    P, P, P, SZ, P]
+    L.rw_solve_workspace_bytes.argtypes = [Dims, I32, I32, I32]
+    L.rw_solve_workspace_bytes.restype = SZ
+    L.rw_solve.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
+                           ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
+    L.rw_downsample.argtypes = [P, ctypes.POINTER(Volume), P, P, P, P]
+    L.rw_classify_bricks.argtypes = [P, P, Dims, I32, I32, P, Dims, ctypes.POINTER(I32),
+                                     ctypes.POINTER(I32), D, D, ctypes.POINTER(Brick), I32,
+                                     ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    L.rw_bricks_workspace_bytes.argtypes = [ctypes.POINTER(Brick), I32, I32, I32, I32]
+    L.rw_bricks_workspace_bytes.restype = SZ
+    L.rw_solve_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, Dims,
+                                  I32, ctypes.POINTER(Brick), I32, ctypes.POINTER(Options), P,
+                                  P, P, SZ, ctypes.POINTER(Stats), P]
+    L.rw_fill_bricks.argtypes = [P, P, Dims, I32, I32, P, Dims, ctypes.POINTER(Brick), I32, P, P]
+    L.rw_backward_workspace_bytes.argtypes = [Dims]
+    L.rw_backward_workspace_bytes.restype = SZ
+    L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
+                                    ctypes.POINTER(Options), I32, P, P, P, ctypes.POINTER(D), P,
+                                    SZ, ctypes.POINTER(Stats), P]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if fn.restype is ctypes.c_int:
+            fn.restype = I32
+    _lib = L
+    return L
+
+
+def _check(status, what="rw call"):
+    if status < 0:
+        detail = lib().rw_last_error().decode()
+        raise RWError(status, f"{what} failed: {lib().rw_status_string(status).decode()}: {detail}")
+    if status == RW_NOT_CONVERGED:
+        warnings.warn(f"{what}: not converged (last iterate returned)", RuntimeWarning)
+    return status
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """Owns an rw_context (private stream, pinned polling buffer)."""
+
+    def __init__(self):
+        p = ctypes.c_void_p()
+        _check(lib().rw_context_create(ctypes.byref(p)), "rw_context_create")
+        self.handle = p
+
+    def close(self):
+        if self.handle:
+            lib().rw_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = None
+
+
+def default_context():
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def _dims(shape):
+    nz, ny, nx = (int(s) for s in shape)
+    return Dims(nx, ny, nz)
+
+
+def make_volume(vol, lo=None, hi=None):
+    """rw_volume for a device tensor (uint16 -> /65535 unless lo/hi given)."""
+    if vol.dtype == torch.uint16:
+        dt = RW_DT_U16
+        lo = 0.0 if lo is None else lo
+        hi = 65535.0 if hi is None else hi
+    elif vol.dtype == torch.float32:
+        dt = RW_DT_F32
+    elif vol.dtype == torch.float64:
+        dt = RW_DT_F64
+    else:
+        raise TypeError(f"unsupported volume dtype {vol.dtype}")
+    if not vol.is_cuda or not vol.is_contiguous():
+        raise ValueError("volume must be a contiguous GPU tensor")
+    if lo is None or hi is None:
+        mm = minmax(vol)
+        lo = mm[0] if lo is None else lo
+        hi = mm[1] if hi is None else hi
+    v = Volume(_ptr(vol), dt, _dims(vol.shape), float(lo), float(hi))
+    v._keep = vol
+    return v
+
+
+def _raw_volume(vol):
+    dt = {torch.uint16: RW_DT_U16, torch.float32: RW_DT_F32, torch.float64: RW_DT_F64}[vol.dtype]
+    v = Volume(_ptr(vol), dt, _dims(vol.shape), 0.0, 1.0)
+    v._keep = vol
+    return v
+
+
+def minmax(vol, ctx=None):
+    """(min, max) of a device volume, reduced by the library's kernels."""
+    ctx = ctx or default_context()
+    out = (ctypes.c_double * 2)()
+    _check(lib().rw_minmax(ctx.handle, ctypes.byref(_raw_volume(vol)), out, _stream()), "rw_minmax")
+    return float(out[0]), float(out[1])
+
+
+def _seeds(labels, K):
+    if labels.dtype != torch.uint8 or not labels.is_cuda or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous uint8 GPU tensor")
+    s = Seeds(_ptr(labels), int(K))
+    s._keep = labels
+    return s
+
+
+def _alloc_ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def build_weights(vol, beta, precision="fp64", labels=None, w_eps=0.0, lo=None, hi=None,
+                  ctx=None):
+    """Materialised weights w[3][nz][ny][nx] (and dinv when labels are given)."""
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    w = torch.empty((3,) + tuple(vol.shape), dtype=dt, device=vol.device)
+    dinv = torch.empty(tuple(vol.shape), dtype=dt, device=vol.device) if labels is not None else None
+    S = _seeds(labels, 1) if labels is not None else None
+    _check(lib().rw_build_weights(ctx.handle, ctypes.byref(V), float(beta), float(w_eps),
+                                  PREC[precision], _ptr(w), _ptr(dinv),
+                                  ctypes.byref(S) if S is not None else None, _stream()),
+           "rw_build_weights")
+    return w, dinv
+
+
+def apply_operator(vol, labels, p, beta, precision="fp64", w_eps=0.0, lo=None, hi=None, ctx=None):
+    """q = L_U p with the CG kernel's matrix-free stencil (p zero on seeds)."""
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, 1)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = p.to(dt).contiguous()
+    q = torch.empty_like(p)
+    nbytes = lib().rw_operator_workspace_bytes(_dims(vol.shape), PREC[precision])
+    ws = _alloc_ws(nbytes, vol.device)
+    _check(lib().rw_apply_operator(ctx.handle, ctypes.byref(V), ctypes.byref(S), float(beta),
+                                   float(w_eps), PREC[precision], _ptr(p), _ptr(q), _ptr(ws),
+                                   nbytes, _stream()), "rw_apply_operator")
+    return q
+
+
+def options(beta, tol=1e-6, precision="fp64", max_iter=20000, max_refine=5, inner_tol=1e-3,
+            solve_all_labels=False, check_interval=16, use_graph=True, kernel_timing=False,
+            w_eps=0.0, x0=None):
+    o = Options()
+    lib().rw_default_options(ctypes.byref(o))
+    o.beta, o.tol, o.w_eps, o.inner_tol = float(beta), float(tol), float(w_eps), float(inner_tol)
+    o.max_iter, o.max_refine = int(max_iter), int(max_refine)
+    o.precision = PREC[precision]
+    o.solve_all_labels = int(bool(solve_all_labels))
+    o.check_interval = int(check_interval)
+    o.use_graph = int(bool(use_graph))
+    o.kernel_timing = int(bool(kernel_timing))
+    o.x0 = _ptr(x0) if x0 is not None else None
+    o._keep = x0
+    return o
+
+
+def solve(vol, labels, K, beta, tol=1e-6, precision="fp64", lo=None, hi=None, argmax=True,
+          ctx=None, workspace=None, return_stats=False, **kw):
+    """Whole-volume random walker: probabilities [K][nz][ny][nx] (+ argmax labels).
+
+    precision "fp64": float64 CG, float64 output; "mixed": float32 CG with
+    float64 dots inside float64 refinement, float32 output.
+    """
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, K)
+    x0 = kw.get("x0")
+    if x0 is not None:
+        kw["x0"] = x0.to(torch.float64).contiguous()
+    o = options(beta, tol, precision, **kw)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    prob = torch.empty((K,) + tuple(vol.shape), dtype=dt, device=vol.device)
+    am = torch.empty(tuple(vol.shape), dtype=torch.uint8, device=vol.device) if argmax else None
+    nbytes = lib().rw_solve_workspace_bytes(_dims(vol.shape), K, o.precision, o.solve_all_labels)
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _alloc_ws(
+        nbytes, vol.device)
+    st = Stats()
+    status = lib().rw_solve(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
+                            _ptr(prob), _ptr(am), _ptr(ws), nbytes, ctypes.byref(st), _stream())
+    _check(status, "rw_solve")
+    out = (prob, am)
+    if return_stats:
+        d = st.to_dict()
+        d["status"] = status
+        return out + (d,)
+    return out
+
+
+def solve_workspace_bytes(shape, K, precision="fp64", solve_all_labels=False):
+    return int(lib().rw_solve_workspace_bytes(_dims(shape), K, PREC[precision],
+                                              int(bool(solve_all_labels))))
