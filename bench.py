@@ -1,0 +1,205 @@
+"""Throughput of the random-walker solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+
+Workload (default "blob512"): a 512^3 float32 volume of 32 random ellipsoid
+blobs (radii U(10, 60), intensities U(0.5, 0.9)) on background 0.2 with
+Gaussian noise sigma 0.08, three labels (two blob classes + background),
+1000 seeds per label inside their regions, beta = 150, min-max normalised,
+stopped at relative residual 1e-6.  Synthetic and seeded; it stands in for
+the paper's cell-volume benchmark (Sec. IV-B, Table III).
+
+One step = one whole solve on inputs already resident in HBM: the device
+min-max reduction plus rw_solve in mixed precision (float32 stencil and
+vectors, float64 dot products, float64 residual refinement).  The plain
+float64 solve of the same volume is timed beside it.
+
+Prints ONE JSON line.  `roofline` is for the dominant kernel (CG pass 2):
+algorithmic bytes per launch over its average launch duration from HIP
+events recorded around every launch on the library's stream.  `cpu_baseline`
+is the C/OpenMP float64 oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("solved voxels/sec at rel. residual 1e-6 (FP32+FP64-dot vs FP64); "
+          "% HBM roofline")
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(n_vox, launches, rhs_iterations, s_g, s_m, s_v, which):
+    """Algorithmic HBM bytes of the CG passes (per voxel: pass 1 reads g, z,
+    p_old and writes p_new: s_g + 3 R s_v; pass 2 reads g, labels, p, x, z and
+    writes x, z: s_g + s_m + 5 R s_v; R = labels still iterating)."""
+    if which == 1:
+        return n_vox * (launches * s_g + 3 * s_v * rhs_iterations)
+    return n_vox * (launches * (s_g + s_m) + 5 * s_v * rhs_iterations)
+
+
+def make_workload(name):
+    from synth import blob_case
+    if name == "blob512":
+        return blob_case(shape=(512, 512, 512), n_blobs=32, K=3, seeds_per_label=1000,
+                         sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=2,
+                         dtype="f32", name="blob512")
+    if name == "blob256":
+        return blob_case(shape=(256, 256, 256), n_blobs=4, K=3, seeds_per_label=125,
+                         sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=2,
+                         dtype="f32", name="blob256")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, gpu_iters_fp64, n_iter, threads):
+    """The float64 C oracle on the same volume: a fixed number of Jacobi-PCG
+    iterations of label 2, scaled to a whole solve with the float64 GPU
+    solve's per-label iteration counts (the oracle needs the same counts to
+    within one).  Returns voxels/s of the oracle."""
+    import numpy as np
+    from oracle import c_oracle, rw_oracle
+    g = rw_oracle.case_g(case)
+    t0 = time.perf_counter()
+    _, it, st = c_oracle.pcg_fixed_iters(g, case.labels, 2, case.beta, n_iter, nthreads=threads)
+    wall = time.perf_counter() - t0
+    setup_s, loop_s = c_oracle.last_timing()
+    t_iter = loop_s / max(it, 1)
+    total_iters = sum(gpu_iters_fp64)
+    t_solve = setup_s * len(gpu_iters_fp64) + t_iter * total_iters
+    n_vox = int(np.prod(case.shape))
+    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, kind="oracle",
+                sample=(f"{it} float64 Jacobi-PCG iterations of label 2 on the full "
+                        f"{case.shape[0]}^3 volume ({wall:.1f} s wall, {t_iter * 1e3:.1f} ms/iter, "
+                        f"set-up {setup_s:.1f} s), scaled to the {total_iters} iterations "
+                        f"({'+'.join(str(i) for i in gpu_iters_fp64)}) of labels 2..K"),
+                seconds_per_solve=t_solve)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="blob512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        raise SystemExit(2)
+
+    import numpy as np
+    import torch
+    from paper_2509_26213_amd import rw
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    case = make_workload(args.workload)
+    print(f"# workload {case.name} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    vol = torch.from_numpy(case.vol).to(dev)
+    lab = torch.from_numpy(case.labels).to(dev)
+    n_vox = int(np.prod(case.shape))
+    K = case.K
+    ctx = rw.default_context()
+    ws = torch.empty(rw.solve_workspace_bytes(case.shape, K, "fp64"), dtype=torch.uint8,
+                     device=dev)
+
+    def step(precision, timing):
+        lo, hi = rw.minmax(vol, ctx=ctx)
+        return rw.solve(vol, lab, K, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
+                        ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing)
+
+    def timed(precision, steps, warmup):
+        for _ in range(warmup):
+            step(precision, True)
+        torch.cuda.synchronize()
+        stats = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            stats.append(step(precision, True)[2])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, stats
+
+    sec_mixed, st_mixed = timed("mixed", args.steps, args.warmup)
+    print(f"# mixed: {sec_mixed * 1e3:.1f} ms/step iters {st_mixed[-1]['iters']} "
+          f"refinements {st_mixed[-1]['refinements']}", file=sys.stderr, flush=True)
+    out_fp64 = None
+    if not args.no_fp64:
+        sec_fp64, st_fp64 = timed("fp64", max(1, args.steps - 1), min(1, args.warmup))
+        print(f"# fp64: {sec_fp64 * 1e3:.1f} ms/step iters {st_fp64[-1]['iters']}",
+              file=sys.stderr, flush=True)
+        s = st_fp64[-1]
+        b2 = pass_bytes(n_vox, s["pass_launches"][1], s["rhs_iterations"], 4, 1, 8, 2)
+        out_fp64 = dict(value=n_vox / sec_fp64, ms_per_step=sec_fp64 * 1e3, iters=s["iters"],
+                        rel_residual=s["rel_residual"],
+                        pass2_gbs=b2 / (s["pass_ms"][1] * 1e-3) / 1e9 if s["pass_ms"][1] else None)
+
+    # roofline of the dominant kernel (pass 2) over the timed mixed steps
+    launches2 = sum(s["pass_launches"][1] for s in st_mixed)
+    launches1 = sum(s["pass_launches"][0] for s in st_mixed)
+    rhs_it = sum(s["rhs_iterations"] for s in st_mixed)
+    ms2 = sum(s["pass_ms"][1] for s in st_mixed)
+    ms1 = sum(s["pass_ms"][0] for s in st_mixed)
+    bytes2 = pass_bytes(n_vox, launches2, rhs_it, 4, 1, 4, 2)
+    bytes1 = pass_bytes(n_vox, launches1, rhs_it, 4, 1, 4, 1)
+    ach2 = bytes2 / (ms2 * 1e-3) / 1e9
+    ach1 = bytes1 / (ms1 * 1e-3) / 1e9
+    s = st_mixed[-1]
+    result = {
+        "metric": METRIC,
+        "value": n_vox / sec_mixed,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64dot",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: {case.shape[0]}x{case.shape[1]}x{case.shape[2]} "
+                               f"float32 blob volume, K={K}, 1000 seeds/label, beta={case.beta}, "
+                               "tol 1e-6, mixed precision (FP32 stencil+vectors, FP64 dots, "
+                               "FP64 refinement)",
+                   "voxels": n_vox, "labels": K, "solved_labels": s["num_solved"]},
+        "roofline": {"bound": "hbm", "kernel": "k_pass2", "achieved": ach2,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "avg_launch_us": ms2 * 1e3 / max(launches2, 1),
+                     "bytes_per_launch": bytes2 / max(launches2, 1)},
+        "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
+                  "avg_launch_us": ms1 * 1e3 / max(launches1, 1)},
+        "stencil_cg_loop_frac": (bytes1 + bytes2) / ((ms1 + ms2) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "iters": s["iters"],
+        "refinements": s["refinements"],
+        "rel_residual": s["rel_residual"],
+        "device_ms": s["device_ms"],
+        "fp64": out_fp64,
+        "mixed_speedup_vs_fp64": (out_fp64["value"] and (n_vox / sec_mixed) / out_fp64["value"])
+        if out_fp64 else None,
+    }
+    if not args.no_cpu_baseline:
+        threads = len(os.sched_getaffinity(0))
+        gpu_iters = out_fp64["iters"] if out_fp64 else s["iters"]
+        try:
+            result["cpu_baseline"] = cpu_baseline(case, gpu_iters, args.cpu_iters, threads)
+        except Exception as e:  # the baseline never hides the GPU result
+            result["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,17 +85,22 @@ typedef struct {
     double beta;          /* >= 0 */
     double w_eps;         /* added to every weight; >= 0 in normal use */
     double tol;           /* relative residual, > 0 (1e-6) */
-    double inner_tol;     /* mixed: relative tolerance of refinement steps after
-                             the first (1e-3); the first inner solve uses tol */
-    int32_t max_iter;     /* CG iterations per solve (20000) */
-    int32_t max_refine;   /* mixed: refinement steps (5) */
+    double inner_tol;     /* mixed, refine_mode 1: relative tolerance of the
+                             refinement steps after the first (1e-3) */
+    double update_delta;  /* mixed, refine_mode 0: the residual is recomputed in
+                             float64 whenever the recurrence residual has fallen
+                             by this factor since the last recomputation (0.1) */
+    int32_t max_iter;     /* CG iterations per label and call (20000) */
+    int32_t max_refine;   /* mixed, refine_mode 1: refinement steps (5) */
     int32_t precision;    /* rw_precision */
     int32_t solve_all_labels; /* 0: solve labels 2..K, background = 1 - sum;
                                  1: solve all K labels independently */
-    int32_t check_interval;   /* CG iterations between convergence polls (even, 16) */
+    int32_t check_interval;   /* CG iterations between convergence polls (16) */
     int32_t use_graph;        /* 1: replay each poll interval as a HIP graph */
     int32_t kernel_timing;    /* 1: time every CG pass with events (no graph) */
-    int32_t reserved;
+    int32_t refine_mode;      /* mixed: 0 = one CG run whose residual is
+                                 recomputed in float64 as it falls (reliable
+                                 updates), 1 = restarted iterative refinement */
     const void* x0;       /* device, initial guess [R][nz][ny][nx] float64 for the
                              solved labels (read on unseeded voxels), or NULL = 0 */
 } rw_options;
@@ -107,7 +112,9 @@ typedef struct {
     int32_t label_status[RW_MAX_LABELS]; /* per solved label: rw_status */
     double rel_residual[RW_MAX_LABELS];  /* final true float64 ||b - Ax|| / ||b|| */
     int32_t num_solved;                  /* R */
-    int32_t refinements;                 /* mixed: residual evaluations after the first */
+    int32_t refinements;                 /* mixed: float64 residual recomputations
+                                            after the first */
+    int32_t tile_by, tile_zc;            /* stencil tile used (64 x by, zc planes) */
     double device_ms;                    /* whole call on the device (events) */
     double loop_ms;                      /* CG iteration loops only */
     /* kernel_timing = 1: summed durations of the CG passes over the iterations

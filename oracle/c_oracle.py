@@ -42,6 +42,11 @@ def lib():
                                           ctypes.c_int, P, P]
         L.orc_pcg_fixed_iters.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_last_timing.argtypes = [P, P]
+        L.orc_last_timing.restype = None
+        L.orc_residual.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P,
+                                   ctypes.c_int]
+        L.orc_residual.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -119,3 +124,21 @@ def pcg_fixed_iters(g, labels, label, beta, n_iter, nthreads=0):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+def last_timing():
+    """(set-up seconds, CG-loop seconds) of the last solve."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_last_timing(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def residual(g, labels, label, beta, x, w_eps=0.0, nthreads=0):
+    """Float64 relative residual ||b - A x|| / ||b|| of a full-grid x of one label."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nz, ny, nx = g.shape
+    dims = np.array([nx, ny, nz], dtype=np.int64)
+    return float(lib().orc_residual(_p(g), _p(labels), _p(dims), float(beta), float(w_eps),
+                                    int(label), _p(x), int(nthreads)))

@@ -46,6 +46,14 @@ static inline int in_vol(const geom_t* G, int64_t x, int64_t y, int64_t z) {
     return x >= 0 && x < G->nx && y >= 0 && y < G->ny && z >= 0 && z < G->nz;
 }
 
+/* wall-clock split of the last orc_solve_box call (set-up, CG loop) */
+static double g_setup_s = 0.0, g_loop_s = 0.0;
+
+void orc_last_timing(double* setup_s, double* loop_s) {
+    *setup_s = g_setup_s;
+    *loop_s = g_loop_s;
+}
+
 static const int DX[6] = {+1, -1, 0, 0, 0, 0};
 static const int DY[6] = {0, 0, +1, -1, 0, 0};
 static const int DZ[6] = {0, 0, 0, 0, +1, -1};
@@ -111,6 +119,7 @@ int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
     double* part = (double*)malloc(sizeof(double) * G.sz * 2);
     uint8_t* unk = (uint8_t*)malloc(n);
     int status = 0;
+    const double t_start = omp_get_wtime();
     if (!w6 || !dinv || !b || !r || !z || !p || !q || !part || !unk) {
         status = -1;
         goto done;
@@ -199,6 +208,8 @@ int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
 
     double bnorm2;
     DOT(b, b, bnorm2);
+    g_setup_s = omp_get_wtime() - t_start;
+    const double t_loop = omp_get_wtime();
     const double nb = sqrt(bnorm2);
     /* x: start from x0 on the unknowns */
 #pragma omp parallel for schedule(static)
@@ -253,6 +264,7 @@ int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
             }
         }
     }
+    g_loop_s = omp_get_wtime() - t_loop;
     /* true relative residual */
     if (rel_true_out) {
         APPLY_A(x_out, q);
@@ -302,3 +314,53 @@ int orc_pcg_fixed_iters(const double* g, const uint8_t* labels, const int64_t di
 }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* Relative float64 residual ||b - A x|| / ||b|| of a given full-volume
+ * solution x of label `label` (seeds' values in x are ignored, the Dirichlet
+ * data [label_j == s] are used).  Returns -1 on a bad argument. */
+double orc_residual(const double* g, const uint8_t* labels, const int64_t dims[3], double beta,
+                    double w_eps, int label, const double* x, int nthreads) {
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx <= 0 || ny <= 0 || nz <= 0) return -1.0;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    double* pr = (double*)calloc((size_t)nz, sizeof(double));
+    double* pb = (double*)calloc((size_t)nz, sizeof(double));
+    if (!pr || !pb) {
+        free(pr);
+        free(pb);
+        return -1.0;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        double sr = 0.0, sb = 0.0;
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t xx = 0; xx < nx; ++xx) {
+                const int64_t i = (z * ny + y) * nx + xx;
+                if (labels[i] != 0) continue;
+                double res = 0.0, bb = 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    const int64_t X = xx + DX[k], Y = y + DY[k], Z = z + DZ[k];
+                    if (X < 0 || X >= nx || Y < 0 || Y >= ny || Z < 0 || Z >= nz) continue;
+                    const int64_t j = (Z * ny + Y) * nx + X;
+                    const double d = g[i] - g[j];
+                    const double w = exp(-beta * d * d) + w_eps;
+                    double xj;
+                    if (labels[j] != 0) {
+                        xj = labels[j] == label ? 1.0 : 0.0;
+                        bb += w * xj;
+                    } else {
+                        xj = x[j];
+                    }
+                    res += w * (xj - x[i]);
+                }
+                sr += res * res;
+                sb += bb * bb;
+            }
+        pr[z] = sr;
+        pb[z] = sb;
+    }
+    const double rr = ordered_sum(pr, nz), bbs = ordered_sum(pb, nz);
+    free(pr);
+    free(pb);
+    return bbs > 0.0 ? sqrt(rr / bbs) : 0.0;
+}

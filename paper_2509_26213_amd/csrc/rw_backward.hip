@@ -1,0 +1,205 @@
+// Adjoint gradient of a loss of one label's random-walker probabilities.
+//
+// Forward: A(w) x_U = b(w) with A = L_U symmetric, b from the seeds.  For a
+// loss L(x), one solve of A lam = dL/dx_U (lam = 0 on seeds) gives, per edge
+// e = (i, j),  dL/dw_e = -(lam_i - lam_j)(x_i - x_j), and with
+// w_e = exp(-beta (g_i - g_j)^2):
+//   dL/dbeta = sum_e (lam_i - lam_j)(x_i - x_j)(g_i - g_j)^2 w_e
+//   dL/dg_i  = sum_{e=(i,j)} 2 beta (lam_i - lam_j)(x_i - x_j)(g_i - g_j) w_e.
+// The adjoint solve reuses the forward CG kernels (float64) with an explicit
+// right-hand side and zero Dirichlet data.
+#include "rw_whole.h"
+
+namespace rw {
+
+constexpr int GRAD_BLOCKS = 1024;
+
+// dL/dg per voxel and per-block partial sums of dL/dbeta (each edge counted
+// once, by its low-side voxel).  gscale = 1 / (hi - lo) turns raw
+// differences into normalised ones.
+template <typename V>
+__global__ __launch_bounds__(256) void k_adjoint_grad(const V* __restrict__ vol,
+                                                      const uint8_t* __restrict__ lab, Geom G,
+                                                      WCoef wc, double gscale, double beta,
+                                                      int label, const double* __restrict__ xf,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ grad_g,
+                                                      double* __restrict__ part) {
+    double acc_b = 0.0;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < G.n; i += 256ll * gridDim.x) {
+        const int z = int(i / G.plane);
+        const int64_t rem = i - (int64_t)z * G.plane;
+        const int y = int(rem / G.nx);
+        const int x = int(rem - (int64_t)y * G.nx);
+        const uint8_t li = lab[i];
+        const double xi = li ? (li == label ? 1.0 : 0.0) : xf[i];
+        const double ai = li ? 0.0 : lam[i];
+        const double vi = (double)vol[i];
+        const bool has[6] = {x > 0, x + 1 < G.nx, y > 0, y + 1 < G.ny, z > 0, z + 1 < G.nz};
+        const int64_t nb[6] = {i - 1, i + 1, i - G.nx, i + G.nx, i - G.plane, i + G.plane};
+        double acc_g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            if (!has[k]) continue;
+            const int64_t j = nb[k];
+            const uint8_t lj = lab[j];
+            const double xj = lj ? (lj == label ? 1.0 : 0.0) : xf[j];
+            const double aj = lj ? 0.0 : lam[j];
+            const double dv = vi - (double)vol[j];
+            const double w = Weight<double>::of(dv, wc);
+            const double ce = (ai - aj) * (xi - xj) * w;
+            const double dg = gscale * dv;
+            acc_g += 2.0 * beta * ce * dg;
+            if (k & 1) acc_b += ce * dg * dg;  // +x, +y, +z: each edge once
+        }
+        if (grad_g) grad_g[i] = acc_g;
+    }
+    double v[1] = {acc_b};
+    block_sum_store<1, 4>(v, part + blockIdx.x, GRAD_BLOCKS);
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_sum1(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ out) {
+    __shared__ double sums[1];
+    sum_partials<1>(part, nb, sums);
+    if (threadIdx.x == 0) out[0] = sums[0];
+}
+
+template <typename V, int BY>
+static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
+                               const rw_options* o, int label, const double* x_full,
+                               const double* grad_x, double* grad_g, double* grad_beta,
+                               void* ws, rw_stats* stats) {
+    const Geom G = make_geom(vol->dims);
+    Carver cv(ws);
+    GroupBuffers B;
+    carve_group(cv, G, 1, false, &B);
+    double* gpart = cv.take<double>(GRAD_BLOCKS + 1);
+    const TileChoice tc = choose_tiles(G, RW_PREC_FP64, 1);
+    rw_options fo = *o;
+    fo.precision = RW_PREC_FP64;
+    WholeSolve<V, double, 1, BY> S;
+    S.ctx = ctx;
+    S.vol = static_cast<const V*>(vol->data);
+    S.lab = lab;
+    S.G = G;
+    S.wc = make_wcoef(vol, o->beta, o->w_eps);
+    S.tm = make_tilemap(G, BY, tc.zc, tc.xcd);
+    S.lab0 = 0;  // zero Dirichlet data: lam = 0 on seeds
+    S.mixed = false;
+    S.reliable = false;
+    S.o = &fo;
+    S.rhs = grad_x;
+    S.B = B;
+    S.zv = static_cast<double*>(B.z);
+    S.p0 = static_cast<double*>(B.p0);
+    S.p1 = static_cast<double*>(B.p1);
+    S.xv = B.x64;
+    rw_status e = S.run(nullptr);
+    if (e) return e;
+    const RhsState& h = S.host_st[0];
+    int code = RW_OK;
+    if (h.status == ST_MAXITER) code = RW_NOT_CONVERGED;
+    else if (h.status == ST_SINGULAR) code = RW_ERR_SINGULAR;
+    else if (h.status == ST_BREAKDOWN) code = RW_ERR_BREAKDOWN;
+    else if (h.status == ST_NONFINITE) code = RW_ERR_NONFINITE;
+    if (stats) {
+        stats->iters[0] = h.iter_total;
+        stats->label_status[0] = code;
+        stats->rel_residual[0] = h.bb > 0 ? std::sqrt(h.rr64 / h.bb) : 0.0;
+        stats->num_solved = 1;
+        stats->loop_ms = S.loop_ms;
+    }
+    if (code < 0) {
+        set_error("adjoint solve failed");
+        return (rw_status)code;
+    }
+    const double span = vol->norm_hi - vol->norm_lo;
+    const double gscale = span > 0 ? 1.0 / span : 0.0;
+    hipLaunchKernelGGL((k_adjoint_grad<V>), dim3(GRAD_BLOCKS), dim3(256), 0, ctx->s,
+                       static_cast<const V*>(vol->data), lab, G, S.wc, gscale, o->beta, label,
+                       x_full, B.x64, grad_g, gpart);
+    hipLaunchKernelGGL(k_sum1, dim3(1), dim3(FIN_THREADS), 0, ctx->s, gpart, GRAD_BLOCKS,
+                       gpart + GRAD_BLOCKS);
+    RW_HIP(hipGetLastError());
+    RW_HIP(hipMemcpyAsync(ctx->host_pinned, gpart + GRAD_BLOCKS, sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->s));
+    RW_HIP(hipStreamSynchronize(ctx->s));
+    if (grad_beta) memcpy(grad_beta, ctx->host_pinned, sizeof(double));
+    return (rw_status)code;
+}
+
+template <typename V>
+static rw_status backward_v(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
+                            const rw_options* o, int label, const double* x_full,
+                            const double* grad_x, double* grad_g, double* grad_beta, void* ws,
+                            rw_stats* stats) {
+    const TileChoice tc = choose_tiles(make_geom(vol->dims), RW_PREC_FP64, 1);
+    if (tc.by == 8)
+        return backward_impl<V, 8>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
+                                   stats);
+    return backward_impl<V, 4>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
+                               stats);
+}
+
+rw_status check_options(const rw_options* o);
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+size_t rw_backward_workspace_bytes(rw_dims dims) {
+    if (dims.nx <= 0 || dims.ny <= 0 || dims.nz <= 0) return 0;
+    Carver cv(nullptr);
+    carve_group(cv, make_geom(dims), 1, false, nullptr);
+    cv.take<double>(GRAD_BLOCKS + 1);
+    return cv.bytes();
+}
+
+rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                            const rw_options* o, int32_t label, const double* x_full,
+                            const double* grad_x, double* grad_g_out, double* grad_beta_out,
+                            void* ws, size_t ws_bytes, rw_stats* stats, void* stream) {
+    if (!ctx) return invalid("context is NULL");
+    rw_status e = check_volume(vol);
+    if (e) return e;
+    if ((e = check_options(o))) return e;
+    if (!seeds || !seeds->labels) return invalid("seeds are NULL");
+    if (seeds->num_labels < 1 || seeds->num_labels > RW_MAX_LABELS)
+        return invalid("num_labels must be in [1, 16]");
+    if (label < 1 || label > seeds->num_labels) return invalid("label out of range");
+    if (!x_full || !grad_x) return invalid("x_full and grad_x are required");
+    const size_t need = rw_backward_workspace_bytes(vol->dims);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace needs " + std::to_string(need) + " bytes");
+        return RW_ERR_WORKSPACE;
+    }
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if ((e = stream_enter(ctx, stream))) return e;
+    unsigned int cnt[256];
+    if ((e = label_counts(ctx, seeds->labels, make_geom(vol->dims).n, cnt))) return e;
+    for (int v = seeds->num_labels + 1; v < 256; ++v)
+        if (cnt[v]) {
+            (void)stream_leave(ctx, stream);
+            return invalid("a seed label exceeds num_labels");
+        }
+    switch (vol->dtype) {
+        case RW_DT_U16:
+            e = backward_v<uint16_t>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+                                     grad_beta_out, ws, stats);
+            break;
+        case RW_DT_F32:
+            e = backward_v<float>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+                                  grad_beta_out, ws, stats);
+            break;
+        default:
+            e = backward_v<double>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+                                   grad_beta_out, ws, stats);
+    }
+    rw_status e2 = stream_leave(ctx, stream);
+    return e ? e : e2;
+}
+
+}  // extern "C"

@@ -236,6 +236,8 @@ void rw_default_options(rw_options* o) {
     o->w_eps = 0.0;
     o->tol = 1e-6;
     o->inner_tol = 1e-3;
+    o->update_delta = 0.1;
+    o->refine_mode = 0;
     o->max_iter = 20000;
     o->max_refine = 5;
     o->precision = RW_PREC_FP64;

@@ -58,27 +58,24 @@ enum : int {
 };
 
 struct RhsState {
-    double rho;      // r.z
-    double alpha;    // rho / p.q
-    double beta;     // rho_new / rho (0 before the first pass)
-    double bb;       // ||b||^2
-    double thresh2;  // stop when r.r <= thresh2
-    double rr;       // last r.r of the CG recurrence
-    double rr64;     // last float64 true residual ||b - A x||^2
-    double pad0;
-    int iter;          // CG iterations of the current inner solve
-    int iter_total;    // summed over inner solves
+    double rho;       // r.z of the current residual
+    double rho_prev;  // r.z before the last update of rho
+    double alpha;     // rho / p.q
+    double beta;      // rho / rho_prev for the next p (0 before the first pass)
+    double bb;        // ||b||^2
+    double thresh2;   // stop iterating when r.r <= thresh2
+    double rr;        // last r.r of the CG recurrence
+    double rr64;      // last float64 true residual ||b - A x||^2
+    double rr_ref;    // r.r right after the last float64 residual refresh
+    int iter;          // CG iterations of the current inner run
+    int iter_total;    // summed over inner runs
     int status;        // ST_*
     int active;        // iterating now
-    int outer_active;  // mixed: refinement still needed after this inner solve
+    int outer_active;  // not final yet (more refinement / refresh may follow)
     int max_iter;
-    int pad1, pad2;
+    int pcur;          // which p buffer (0/1) holds the current search direction
+    int refreshes;     // float64 residual refreshes (mixed precision)
 };
-
-// Tile of the 2.5D stencil kernels: 64 x 4 threads, each walks z.
-constexpr int BX = 64;
-constexpr int BY = 4;
-constexpr int NT = BX * BY;
 
 // Workspace carving helper.
 struct Carver {

@@ -15,11 +15,19 @@ rw_status stream_leave(rw_context* ctx, void* user);
 rw_status label_counts(rw_context* ctx, const uint8_t* lab, int64_t n, unsigned int* host256);
 rw_status ensure_events(rw_context* ctx, size_t n);
 
-// Sum NQ per-thread values over a 256-thread block in a fixed order (wave
-// butterfly, then the four wave totals in wave order); thread 0..NQ-1 write
-// out[q].  Every thread of the block must call it.
-template <int NQ>
-__device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* __restrict__ out) {
+// Tile shape of the stencil kernels (64 x by columns, zc planes, XCD-aware
+// tile order on/off), from the tuning table or the environment.
+struct TileChoice {
+    int by, zc, xcd;
+};
+TileChoice tuned_tiles(const Geom& G, int precision, int R);
+
+// Sum NQ per-thread values over a block of NW waves in a fixed order (wave
+// butterfly, then the wave totals in wave order); threads 0..NQ-1 write
+// out[q * stride].  Every thread of the block must call it.
+template <int NQ, int NW>
+__device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* __restrict__ out,
+                                                int64_t stride) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
@@ -30,7 +38,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* __restr
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
         v[q] = a;
     }
-    __shared__ double sh[NT / 64][NQ];
+    __shared__ double sh[NW][NQ];
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sh[wid][q] = v[q];
@@ -39,36 +47,74 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* __restr
     if (tid < NQ) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) s += sh[w][tid];
-        out[tid] = s;
+        for (int w = 0; w < NW; ++w) s += sh[w][tid];
+        out[tid * stride] = s;
     }
 }
 
-// Fixed-order sum over blocks of the NQ-quantity partials; result in sums[]
-// (shared) visible to every thread after return.  One 256-thread block.
+// Fixed-order sum over blocks of partials laid out [NQ][nblocks]; result in
+// sums[] (shared) visible to every thread after return.  One block of
+// FIN_THREADS threads.
+constexpr int FIN_THREADS = 1024;
+
 template <int NQ>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nblocks,
                                              double* sums) {
-    __shared__ double sh[256];
+    constexpr int NW = FIN_THREADS / 64;
+    __shared__ double sh[NW][NQ];
     const int tid = threadIdx.x;
     double a[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) a[q] = 0.0;
-    for (int b = tid; b < nblocks; b += 256) {
+    for (int b = tid; b < nblocks; b += FIN_THREADS) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) a[q] += part[(int64_t)b * NQ + q];
+        for (int q = 0; q < NQ; ++q) a[q] += part[(int64_t)q * nblocks + b];
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        sh[tid] = a[q];
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) sh[tid] += sh[tid + o];
-            __syncthreads();
-        }
-        if (tid == 0) sums[q] = sh[0];
-        __syncthreads();
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_xor(a[q], off, 64);
     }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sh[tid >> 6][q] = a[q];
+    }
+    __syncthreads();
+    if (tid < NQ) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += sh[w][tid];
+        sums[tid] = s;
+    }
+    __syncthreads();
+}
+
+// Tile order of the 2.5D stencil kernels: tiles of 64 x BY columns by zc
+// planes, tx fastest, then ty, then tz.  With xcd = 1 the grid has 8 * per
+// blocks and block b takes tile (b % 8) * per + b / 8: the hardware deals
+// blocks to the eight XCDs round-robin, so each XCD walks one contiguous
+// range of tiles and the neighbour rows a tile re-reads were fetched into
+// the same XCD's L2 by the tile before it.
+struct TileMap {
+    int gx, gy, gz, zc, tiles, per, xcd, by;
+    __device__ __forceinline__ int tile(int b) const {
+        if (!xcd) return b < tiles ? b : -1;
+        const int t = (b & 7) * per + (b >> 3);
+        return t < tiles ? t : -1;
+    }
+    __host__ __device__ int blocks() const { return xcd ? 8 * per : tiles; }
+};
+
+inline TileMap make_tilemap(const Geom& G, int by, int zc, int xcd) {
+    TileMap m;
+    m.by = by;
+    m.zc = zc;
+    m.gx = (G.nx + 63) / 64;
+    m.gy = (G.ny + by - 1) / by;
+    m.gz = (G.nz + zc - 1) / zc;
+    m.tiles = m.gx * m.gy * m.gz;
+    m.per = (m.tiles + 7) / 8;
+    m.xcd = xcd;
+    return m;
 }
 
 }  // namespace rw

@@ -21,10 +21,4 @@ rw_status rw_fill_bricks(rw_context*, const float*, rw_dims, int32_t, int32_t, c
                          rw_dims, const rw_brick*, int32_t, float*, void*) {
     return RW_ERR_UNSUPPORTED;
 }
-size_t rw_backward_workspace_bytes(rw_dims) { return 0; }
-rw_status rw_solve_backward(rw_context*, const rw_volume*, const rw_seeds*, const rw_options*,
-                            int32_t, const double*, const double*, double*, double*, void*, size_t,
-                            rw_stats*, void*) {
-    return RW_ERR_UNSUPPORTED;
-}
 }

@@ -62,11 +62,12 @@ class Seeds(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("w_eps", ctypes.c_double), ("tol", ctypes.c_double),
-                ("inner_tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("solve_all_labels", ctypes.c_int32), ("check_interval", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("kernel_timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("x0", ctypes.c_void_p)]
+                ("inner_tol", ctypes.c_double), ("update_delta", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("solve_all_labels", ctypes.c_int32),
+                ("check_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("kernel_timing", ctypes.c_int32), ("refine_mode", ctypes.c_int32),
+                ("x0", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -74,6 +75,7 @@ class Stats(ctypes.Structure):
                 ("label_status", ctypes.c_int32 * RW_MAX_LABELS),
                 ("rel_residual", ctypes.c_double * RW_MAX_LABELS),
                 ("num_solved", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("tile_by", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
                 ("device_ms", ctypes.c_double), ("loop_ms", ctypes.c_double),
                 ("pass_ms", ctypes.c_double * 2), ("pass_launches", ctypes.c_int64 * 2),
                 ("rhs_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
@@ -83,7 +85,8 @@ class Stats(ctypes.Structure):
         R = self.num_solved
         return dict(iters=list(self.iters[:R]), label_status=list(self.label_status[:R]),
                     rel_residual=list(self.rel_residual[:R]), num_solved=R,
-                    refinements=self.refinements, device_ms=self.device_ms,
+                    refinements=self.refinements, tile=(self.tile_by, self.tile_zc),
+                    device_ms=self.device_ms,
                     loop_ms=self.loop_ms, pass_ms=list(self.pass_ms),
                     pass_launches=list(self.pass_launches), rhs_iterations=self.rhs_iterations,
                     active_bricks=self.active_bricks, unknowns=self.unknowns)
@@ -284,7 +287,7 @@ def apply_operator(vol, labels, p, beta, precision="fp64", w_eps=0.0, lo=None, h
 
 def options(beta, tol=1e-6, precision="fp64", max_iter=20000, max_refine=5, inner_tol=1e-3,
             solve_all_labels=False, check_interval=16, use_graph=True, kernel_timing=False,
-            w_eps=0.0, x0=None):
+            w_eps=0.0, x0=None, refine_mode="reliable", update_delta=0.1):
     o = Options()
     lib().rw_default_options(ctypes.byref(o))
     o.beta, o.tol, o.w_eps, o.inner_tol = float(beta), float(tol), float(w_eps), float(inner_tol)
@@ -294,6 +297,8 @@ def options(beta, tol=1e-6, precision="fp64", max_iter=20000, max_refine=5, inne
     o.check_interval = int(check_interval)
     o.use_graph = int(bool(use_graph))
     o.kernel_timing = int(bool(kernel_timing))
+    o.refine_mode = {"reliable": 0, "restart": 1}[refine_mode]
+    o.update_delta = float(update_delta)
     o.x0 = _ptr(x0) if x0 is not None else None
     o._keep = x0
     return o

@@ -114,14 +114,16 @@ def test_sphere64_mixed_parity(rw, sphere64):
     assert st["status"] == 0 and st["rel_residual"][0] <= 1e-6
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_blob_ragged_three_labels(rw, precision):
+@pytest.mark.parametrize("precision,mode", [("fp64", "reliable"), ("mixed", "reliable"),
+                                            ("mixed", "restart")])
+def test_blob_ragged_three_labels(rw, precision, mode):
     c = blob_case(shape=(37, 45, 93), n_blobs=6, K=3, seeds_per_label=40, sigma=0.08,
                   rmin=4, rmax=14, seed=11)
     ref, info = _oracle_same(c)
     vol, lab = _case_tensors(c)
     prob, am, st = rw.solve(vol, lab, c.K, c.beta, tol=1e-6, precision=precision,
-                            return_stats=True)
+                            return_stats=True, refine_mode=mode)
+    assert max(st["rel_residual"]) <= 1.01e-6
     assert_parity(host(prob), ref, what=f"blob {precision}")
     seeded = c.labels > 0
     P = host(prob)
@@ -138,6 +140,23 @@ def test_u16_volume_and_solve_all_labels(rw):
     P = host(prob)
     assert_parity(P, ref, what="u16 all labels")
     assert np.max(np.abs(P.sum(0) - 1)) < 1e-4
+
+
+@pytest.mark.parametrize("by,zc,xcd", [(4, 4, 0), (8, 16, 1), (4, 64, 1), (8, 5, 1)])
+def test_tile_shapes_agree(rw, monkeypatch, by, zc, xcd):
+    """Every tile shape gives the same float64 iterate up to rounding order."""
+    c = blob_case(shape=(29, 70, 131), n_blobs=5, K=3, seeds_per_label=30, sigma=0.08,
+                  rmin=4, rmax=12, seed=13)
+    ref, _ = _oracle_same(c)
+    vol, lab = _case_tensors(c)
+    monkeypatch.setenv("RW_TILE_BY", str(by))
+    monkeypatch.setenv("RW_TILE_ZC", str(zc))
+    monkeypatch.setenv("RW_TILE_XCD", str(xcd))
+    for precision in ("fp64", "mixed"):
+        prob, _, st = rw.solve(vol, lab, 3, c.beta, tol=1e-6, precision=precision,
+                               return_stats=True)
+        assert st["tile"][0] == by
+        assert_parity(host(prob), ref, what=f"tile {by}x{zc} {precision}")
 
 
 def test_graph_and_plain_launches_bitwise_equal(rw):
