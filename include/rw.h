@@ -123,6 +123,11 @@ typedef struct {
     double pass_ms[2];
     int64_t pass_launches[2];
     int64_t rhs_iterations;
+    /* algorithmic work of the CG passes: sum over the launches that did work
+       of the voxels of the boxes (volume or bricks) with a label iterating,
+       and of those voxels times the number of labels iterating */
+    int64_t box_voxel_iterations;
+    int64_t rhs_voxel_iterations;
     int64_t active_bricks;               /* brick solves: bricks solved */
     int64_t unknowns;                    /* unseeded voxels solved for */
 } rw_stats;
@@ -179,55 +184,65 @@ rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                    const rw_options* opts, void* prob_out, uint8_t* argmax_out, void* ws,
                    size_t ws_bytes, rw_stats* stats, void* stream);
 
-/* One LOD step: g_out[c] = mean of the (up to) 2x2x2 fine values of g
- * (normalised float32 of the input volume for level 0, else the previous
- * level's float32); coarse size ceil(n/2).  seeds_out (optional): coarse label
- * map, label s iff the block holds seeds of s only (conflicts -> 0). */
+/* One LOD step (levels of detail built by smoothing and downsampling, the
+ * paper's Sec. III-D): g_out[c] = mean of the (up to) 2x2x2 fine values of g
+ * in block c, g the normalised intensity of `fine` (pass a previous level's
+ * output as RW_DT_F32/F64 with norm_lo 0, norm_hi 1); coarse size ceil(n/2)
+ * per axis.  out_dtype: RW_DT_F32 or RW_DT_F64 (g_out's type).
+ * labels_out (optional, needs fine_labels): coarse seed map, label s iff the
+ * block holds seeds of s and of no other label (conflicts -> 0). */
 rw_status rw_downsample(rw_context* ctx, const rw_volume* fine, const uint8_t* fine_labels,
-                        float* g_out, uint8_t* labels_out, void* stream);
+                        int32_t out_dtype, void* g_out, uint8_t* labels_out, void* stream);
 
-/* Brick activity on the fine grid from coarse probabilities.
- * coarse_prob: [K][coarse dims] float32; upsampling factor f (fine index i
- *   <-> coarse coordinate (i + 0.5)/f - 0.5, clamped, trilinear).
- * The fine grid is tiled into bricks of brick_size with the first cut at
- *   grid_offset (0 = none) per axis; a brick is active iff a voxel of the brick
- *   or of its face shell has lo_thr < p_s < hi_thr for some label, or a seed
- *   in the brick differs from the upsampled argmax.
- * bricks_out: host, capacity >= number of candidate bricks (n_candidates);
- *   receives the active bricks, sorted by decreasing voxel count, ties by
- *   position.  n_active: host. */
-rw_status rw_classify_bricks(rw_context* ctx, const float* coarse_prob, rw_dims coarse_dims,
-                             int32_t num_labels, int32_t factor, const uint8_t* fine_labels,
-                             rw_dims fine_dims, const int32_t brick_size[3],
-                             const int32_t grid_offset[3], double lo_thr, double hi_thr,
-                             rw_brick* bricks_out, int32_t capacity, int32_t* n_candidates,
-                             int32_t* n_active, void* stream);
+/* Brick activity from coarse probabilities (coarse-to-fine step of the
+ * hierarchical random walker, Sec. IV-B).
+ * coarse_prob: [K][coarse dims], float32 (coarse_dtype RW_DT_F32) or float64.
+ * Upsampling: fine index i <-> coarse coordinate (i + 0.5)/factor - 0.5,
+ *   clamped to [0, n_c - 1], trilinear, in float64.
+ * Tiling: per axis cuts at grid_offset (0 = none), then every brick_size
+ *   voxels; bricks_out (host, capacity >= candidates) receives every
+ *   candidate brick in z-major grid order, active_out (host) one flag each.
+ * Active: some voxel of the brick or of its in-volume face shell has
+ *   lo_thr < p_s < hi_thr (strict) for some label s, or a seed in the brick
+ *   differs from the upsampled argmax (lowest label on ties). */
+rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
+                             rw_dims coarse_dims, int32_t num_labels, int32_t factor,
+                             const uint8_t* fine_labels, rw_dims fine_dims,
+                             const int32_t brick_size[3] /* x, y, z */,
+                             const int32_t grid_offset[3] /* x, y, z */, double lo_thr,
+                             double hi_thr, rw_brick* bricks_out, uint8_t* active_out,
+                             int32_t capacity, int32_t* n_candidates, void* stream);
 
-/* Batched solve of many bricks of the fine level in one persistent launch.
- * Each brick solves the random walker restricted to the brick: unknowns are
- * its unseeded voxels; Dirichlet data are its seeds and every in-volume face
+/* Batched solve of many bricks of the fine level in one set of launches
+ * (each CG pass of every brick in one launch, over a compacted list of the
+ * tiles of the bricks still iterating; per-brick, per-label convergence).
+ * Each brick solves the random walker restricted to it: unknowns are its
+ * unseeded voxels; Dirichlet data are its seeds and every in-volume face
  * neighbour outside it (seed value if seeded, else the upsampled coarse
  * probability).  x0 = the upsampled coarse probabilities; stopping
- * ||r|| <= tol ||b|| per brick and label.  Precision MIXED (float32 CG,
- * float64 dots) or FP64.
+ * ||r|| <= tol ||b|| per brick and label (b of the brick system).
+ * Precision MIXED (float32 CG, float64 dots, float64 residual refreshes) or
+ * FP64; opts->x0 is ignored.  Bricks need not be disjoint from seeds; they
+ * must lie inside the volume.
  * bricks: host array of n_bricks.  prob_out: [K][nz][ny][nx] float32 fine
- *   grid: brick voxels are overwritten; other voxels untouched.
- * brick_iters: NULL or host int32 [n_bricks][R] iterations per brick/label.
+ *   grid: the voxels of the bricks are overwritten, other voxels untouched.
+ * brick_iters: NULL or host int32 [n_bricks][R] CG iterations per brick/label.
  * ws: rw_bricks_workspace_bytes(...). */
 size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32_t num_labels,
                                  int32_t precision, int32_t solve_all_labels);
 rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* fine_seeds,
-                          const float* coarse_prob, rw_dims coarse_dims, int32_t factor,
-                          const rw_brick* bricks, int32_t n_bricks, const rw_options* opts,
-                          float* prob_out, int32_t* brick_iters, void* ws, size_t ws_bytes,
-                          rw_stats* stats, void* stream);
+                          const void* coarse_prob, int32_t coarse_dtype, rw_dims coarse_dims,
+                          int32_t factor, const rw_brick* bricks, int32_t n_bricks,
+                          const rw_options* opts, float* prob_out, int32_t* brick_iters,
+                          void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
 
-/* Upsampled coarse probabilities written into the fine grid for every
- * voxel of the listed bricks (the inactive bricks), seeds exact. */
-rw_status rw_fill_bricks(rw_context* ctx, const float* coarse_prob, rw_dims coarse_dims,
-                         int32_t num_labels, int32_t factor, const uint8_t* fine_labels,
-                         rw_dims fine_dims, const rw_brick* bricks, int32_t n_bricks,
-                         float* prob_out, void* stream);
+/* Upsampled coarse probabilities written into the fine grid for every voxel
+ * of the listed bricks (the inactive ones), seeds exact.  prob_out: [K][fine]
+ * float32. */
+rw_status rw_fill_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
+                         rw_dims coarse_dims, int32_t num_labels, int32_t factor,
+                         const uint8_t* fine_labels, rw_dims fine_dims, const rw_brick* bricks,
+                         int32_t n_bricks, float* prob_out, void* stream);
 
 /* Adjoint gradient of a loss L(x^s) of one solved label s (float64).
  * x_full: [nz][ny][nx] the forward solution of label s (seeds exact).

@@ -194,6 +194,28 @@ rw_status label_counts(rw_context* ctx, const uint8_t* lab, int64_t n, unsigned 
     return RW_OK;
 }
 
+rw_status ensure_host_pinned(rw_context* ctx, size_t bytes) {
+    if (ctx->host_pinned_bytes >= bytes) return RW_OK;
+    RW_HIP(hipStreamSynchronize(ctx->s));
+    if (ctx->host_pinned) RW_HIP(hipHostFree(ctx->host_pinned));
+    ctx->host_pinned = nullptr;
+    ctx->host_pinned_bytes = 0;
+    RW_HIP(hipHostMalloc(&ctx->host_pinned, bytes, hipHostMallocDefault));
+    ctx->host_pinned_bytes = bytes;
+    return RW_OK;
+}
+
+rw_status ensure_dev_small(rw_context* ctx, size_t bytes) {
+    if (ctx->dev_small_bytes >= bytes) return RW_OK;
+    RW_HIP(hipStreamSynchronize(ctx->s));
+    if (ctx->dev_small) RW_HIP(hipFree(ctx->dev_small));
+    ctx->dev_small = nullptr;
+    ctx->dev_small_bytes = 0;
+    RW_HIP(hipMalloc(&ctx->dev_small, bytes));
+    ctx->dev_small_bytes = bytes;
+    return RW_OK;
+}
+
 rw_status ensure_events(rw_context* ctx, size_t n) {
     while (ctx->pool.size() < n) {
         hipEvent_t e;

@@ -14,6 +14,9 @@ rw_status stream_enter(rw_context* ctx, void* user);
 rw_status stream_leave(rw_context* ctx, void* user);
 rw_status label_counts(rw_context* ctx, const uint8_t* lab, int64_t n, unsigned int* host256);
 rw_status ensure_events(rw_context* ctx, size_t n);
+// Grow the context's pinned host buffer / small device scratch (contents lost).
+rw_status ensure_host_pinned(rw_context* ctx, size_t bytes);
+rw_status ensure_dev_small(rw_context* ctx, size_t bytes);
 
 // Tile shape of the stencil kernels (64 x by columns, zc planes, XCD-aware
 // tile order on/off), from the tuning table or the environment.

@@ -312,6 +312,7 @@ struct WholeSolve {
     double pass_ms[2] = {0, 0};
     int64_t launches[2] = {0, 0};
     int64_t rhs_iters = 0;
+    int64_t box_vox = 0, rhs_vox = 0;
 
     dim3 grid() const { return dim3(unsigned(tm.blocks())); }
     WholeTiles ts() const {
@@ -445,9 +446,11 @@ struct WholeSolve {
             for (int r = 0; r < R; ++r) {
                 const int d = host_st[r].iter_total - prev_iter[r];
                 rhs_iters += d;
+                rhs_vox += (int64_t)d * G.n;
                 kmax = std::max(kmax, d);
                 prev_iter[r] = host_st[r].iter_total;
             }
+            box_vox += (int64_t)kmax * G.n;
             if (timing) {
                 for (int k = 0; k < kmax; ++k) {
                     float a = 0.f, b = 0.f;
@@ -593,6 +596,8 @@ inline rw_status run_group_by(rw_context* ctx, const rw_volume* vol, const uint8
         stats->pass_launches[0] += S.launches[0];
         stats->pass_launches[1] += S.launches[1];
         stats->rhs_iterations += S.rhs_iters;
+        stats->box_voxel_iterations += S.box_vox;
+        stats->rhs_voxel_iterations += S.rhs_vox;
         stats->refinements += S.refreshes();
         stats->tile_by = BY;
         stats->tile_zc = S.tm.zc;

@@ -78,7 +78,8 @@ class Stats(ctypes.Structure):
                 ("tile_by", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
                 ("device_ms", ctypes.c_double), ("loop_ms", ctypes.c_double),
                 ("pass_ms", ctypes.c_double * 2), ("pass_launches", ctypes.c_int64 * 2),
-                ("rhs_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
+                ("rhs_iterations", ctypes.c_int64), ("box_voxel_iterations", ctypes.c_int64),
+                ("rhs_voxel_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
                 ("unknowns", ctypes.c_int64)]
 
     def to_dict(self):
@@ -89,6 +90,8 @@ class Stats(ctypes.Structure):
                     device_ms=self.device_ms,
                     loop_ms=self.loop_ms, pass_ms=list(self.pass_ms),
                     pass_launches=list(self.pass_launches), rhs_iterations=self.rhs_iterations,
+                    box_voxel_iterations=self.box_voxel_iterations,
+                    rhs_voxel_iterations=self.rhs_voxel_iterations,
                     active_bricks=self.active_bricks, unknowns=self.unknowns)
 
 
@@ -128,16 +131,17 @@ def lib():
     L.rw_solve_workspace_bytes.restype = SZ
     L.rw_solve.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                            ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
-    L.rw_downsample.argtypes = [P, ctypes.POINTER(Volume), P, P, P, P]
-    L.rw_classify_bricks.argtypes = [P, P, Dims, I32, I32, P, Dims, ctypes.POINTER(I32),
-                                     ctypes.POINTER(I32), D, D, ctypes.POINTER(Brick), I32,
-                                     ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    L.rw_downsample.argtypes = [P, ctypes.POINTER(Volume), P, I32, P, P, P]
+    L.rw_classify_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(I32),
+                                     ctypes.POINTER(I32), D, D, ctypes.POINTER(Brick), P, I32,
+                                     ctypes.POINTER(I32), P]
     L.rw_bricks_workspace_bytes.argtypes = [ctypes.POINTER(Brick), I32, I32, I32, I32]
     L.rw_bricks_workspace_bytes.restype = SZ
-    L.rw_solve_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, Dims,
+    L.rw_solve_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, I32, Dims,
                                   I32, ctypes.POINTER(Brick), I32, ctypes.POINTER(Options), P,
                                   P, P, SZ, ctypes.POINTER(Stats), P]
-    L.rw_fill_bricks.argtypes = [P, P, Dims, I32, I32, P, Dims, ctypes.POINTER(Brick), I32, P, P]
+    L.rw_fill_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(Brick), I32,
+                                 P, P]
     L.rw_backward_workspace_bytes.argtypes = [Dims]
     L.rw_backward_workspace_bytes.restype = SZ
     L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
@@ -339,3 +343,196 @@ def solve(vol, labels, K, beta, tol=1e-6, precision="fp64", lo=None, hi=None, ar
 def solve_workspace_bytes(shape, K, precision="fp64", solve_all_labels=False):
     return int(lib().rw_solve_workspace_bytes(_dims(shape), K, PREC[precision],
                                               int(bool(solve_all_labels))))
+
+
+# ---------------------------------------------------------------- hierarchy
+
+def _dt_code(t):
+    return {torch.float32: RW_DT_F32, torch.float64: RW_DT_F64}[t.dtype]
+
+
+def downsample(g, labels=None, lo=None, hi=None, out_dtype=torch.float32, ctx=None):
+    """One LOD step: 2x2x2 means of the normalised intensities (+ coarse seeds)."""
+    ctx = ctx or default_context()
+    V = make_volume(g, lo, hi)
+    cz, cy, cx = ((int(n) + 1) // 2 for n in g.shape)
+    out = torch.empty((cz, cy, cx), dtype=out_dtype, device=g.device)
+    lab_out = torch.empty((cz, cy, cx), dtype=torch.uint8, device=g.device) if labels is not None else None
+    if labels is not None and (labels.dtype != torch.uint8 or not labels.is_contiguous()):
+        raise ValueError("labels must be contiguous uint8")
+    _check(lib().rw_downsample(ctx.handle, ctypes.byref(V), _ptr(labels), _dt_code(out), _ptr(out),
+                               _ptr(lab_out), _stream()), "rw_downsample")
+    return out, lab_out
+
+
+def _bricks_array(bricks):
+    arr = (Brick * max(len(bricks), 1))()
+    for i, (o, sz) in enumerate(bricks):
+        arr[i] = Brick(int(o[2]), int(o[1]), int(o[0]), int(sz[2]), int(sz[1]), int(sz[0]))
+    return arr
+
+
+def _from_brick(b):
+    return ((b.oz, b.oy, b.ox), (b.sz, b.sy, b.sx))
+
+
+def classify_bricks(coarse_prob, labels, factor, brick=(64, 64, 64), offset=(0, 0, 0),
+                    lo_thr=0.02, hi_thr=0.98, ctx=None):
+    """Candidate bricks (z-major grid order, (origin_zyx, size_zyx)) and their
+    activity flags.  brick and offset are given (z, y, x)."""
+    ctx = ctx or default_context()
+    K = int(coarse_prob.shape[0])
+    cd = _dims(coarse_prob.shape[1:])
+    fd = _dims(labels.shape)
+    bs = (ctypes.c_int32 * 3)(int(brick[2]), int(brick[1]), int(brick[0]))
+    go = (ctypes.c_int32 * 3)(int(offset[2]), int(offset[1]), int(offset[0]))
+    ncand = ctypes.c_int32(0)
+    st = lib().rw_classify_bricks(ctx.handle, _ptr(coarse_prob), _dt_code(coarse_prob), cd, K,
+                                  int(factor), _ptr(labels), fd, bs, go, float(lo_thr),
+                                  float(hi_thr), None, None, 0, ctypes.byref(ncand), _stream())
+    n = ncand.value
+    arr = (Brick * n)()
+    flags = (ctypes.c_uint8 * n)()
+    _check(lib().rw_classify_bricks(ctx.handle, _ptr(coarse_prob), _dt_code(coarse_prob), cd, K,
+                                    int(factor), _ptr(labels), fd, bs, go, float(lo_thr),
+                                    float(hi_thr), arr, flags, n, ctypes.byref(ncand), _stream()),
+           "rw_classify_bricks")
+    return [_from_brick(arr[i]) for i in range(n)], [bool(flags[i]) for i in range(n)]
+
+
+def fill_bricks(coarse_prob, labels, factor, bricks, prob_out, ctx=None):
+    """Upsampled coarse probabilities (seeds exact) into the listed bricks of prob_out."""
+    ctx = ctx or default_context()
+    arr = _bricks_array(bricks)
+    _check(lib().rw_fill_bricks(ctx.handle, _ptr(coarse_prob), _dt_code(coarse_prob),
+                                _dims(coarse_prob.shape[1:]), int(coarse_prob.shape[0]), int(factor),
+                                _ptr(labels), _dims(labels.shape), arr, len(bricks), _ptr(prob_out),
+                                _stream()), "rw_fill_bricks")
+    return prob_out
+
+
+def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=None, tol=1e-6,
+                 precision="mixed", lo=None, hi=None, ctx=None, return_stats=False, **kw):
+    """Batched brick solves; returns (prob_out [K][grid] float32, iters [n][R])."""
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, K)
+    o = options(beta, tol, precision, **kw)
+    if prob_out is None:
+        prob_out = torch.zeros((K,) + tuple(vol.shape), dtype=torch.float32, device=vol.device)
+    arr = _bricks_array(bricks)
+    n = len(bricks)
+    R = K if o.solve_all_labels else K - 1
+    nbytes = lib().rw_bricks_workspace_bytes(arr, n, K, o.precision, o.solve_all_labels)
+    ws = _alloc_ws(nbytes, vol.device)
+    iters = (ctypes.c_int32 * max(n * R, 1))()
+    st = Stats()
+    status = lib().rw_solve_bricks(ctx.handle, ctypes.byref(V), ctypes.byref(S), _ptr(coarse_prob),
+                                   _dt_code(coarse_prob), _dims(coarse_prob.shape[1:]), int(factor),
+                                   arr, n, ctypes.byref(o), _ptr(prob_out), iters, _ptr(ws), nbytes,
+                                   ctypes.byref(st), _stream())
+    _check(status, "rw_solve_bricks")
+    it = [[iters[i * R + r] for r in range(R)] for i in range(n)]
+    if return_stats:
+        d = st.to_dict()
+        d["status"] = status
+        return prob_out, it, d
+    return prob_out, it
+
+
+def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offset=(0, 0, 0),
+                       tol=1e-6, coarse_precision="fp64", brick_precision="mixed", lo=None,
+                       hi=None, lo_thr=0.02, hi_thr=0.98, ctx=None, return_info=False):
+    """Coarse-to-fine random walker: LOD levels, whole coarse solve, brick
+    classification, batched solve of the uncertain bricks, upsampled fill of
+    the others.  Every step runs in the library; this only sequences calls."""
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    g, lab = vol, labels
+    glo, ghi = V.norm_lo, V.norm_hi
+    for _ in range(levels):
+        g, lab = downsample(g, lab, lo=glo, hi=ghi, out_dtype=torch.float64, ctx=ctx)
+        glo, ghi = 0.0, 1.0
+    coarse, _, cst = solve(g, lab, K, beta, tol=tol, precision=coarse_precision, lo=0.0, hi=1.0,
+                           argmax=False, ctx=ctx, return_stats=True)
+    f = 2 ** levels
+    cands, active = classify_bricks(coarse, labels, f, brick, offset, lo_thr, hi_thr, ctx=ctx)
+    act = [b for b, a in zip(cands, active) if a]
+    ina = [b for b, a in zip(cands, active) if not a]
+    prob = torch.empty((K,) + tuple(vol.shape), dtype=torch.float32, device=vol.device)
+    if ina:
+        fill_bricks(coarse, labels, f, ina, prob, ctx=ctx)
+    bst = None
+    iters = []
+    if act:
+        _, iters, bst = solve_bricks(vol, labels, K, beta, coarse, f, act, prob_out=prob, tol=tol,
+                                     precision=brick_precision, lo=V.norm_lo, hi=V.norm_hi,
+                                     ctx=ctx, return_stats=True)
+    if return_info:
+        return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
+                          brick_iters=iters, brick_stats=bst)
+    return prob
+
+
+# ---------------------------------------------------------------- gradients
+
+def solve_backward(g, labels, K, beta, label, x_full, grad_x, tol=1e-10, lo=0.0, hi=1.0,
+                   ctx=None, **kw):
+    """Adjoint gradient (dL/dg on the normalised intensities, dL/dbeta) of a
+    loss of label `label`'s probability map x_full (float64) with dL/dx grad_x."""
+    ctx = ctx or default_context()
+    V = make_volume(g, lo, hi)
+    S = _seeds(labels, K)
+    o = options(beta, tol, "fp64", **kw)
+    x_full = x_full.to(torch.float64).contiguous()
+    grad_x = grad_x.to(torch.float64).contiguous()
+    grad_g = torch.empty(tuple(g.shape), dtype=torch.float64, device=g.device)
+    gb = ctypes.c_double(0.0)
+    nbytes = lib().rw_backward_workspace_bytes(_dims(g.shape))
+    ws = _alloc_ws(nbytes, g.device)
+    st = Stats()
+    _check(lib().rw_solve_backward(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
+                                   int(label), _ptr(x_full), _ptr(grad_x), _ptr(grad_g),
+                                   ctypes.byref(gb), _ptr(ws), nbytes, ctypes.byref(st), _stream()),
+           "rw_solve_backward")
+    return grad_g, gb.value
+
+
+class RandomWalkerFn(torch.autograd.Function):
+    """Probabilities [K][grid] of a float64 random-walker solve of normalised
+    intensities g (GPU, float64) with parameter beta; differentiable in g and
+    beta through one adjoint solve per solved label."""
+
+    @staticmethod
+    def forward(ctx, g, beta, labels, K, tol, solve_all_labels):
+        b = float(beta)
+        prob, _ = solve(g.contiguous(), labels, K, b, tol=tol, precision="fp64", lo=0.0, hi=1.0,
+                        argmax=False, solve_all_labels=solve_all_labels)
+        ctx.save_for_backward(g, labels, prob)
+        ctx.K, ctx.beta, ctx.tol, ctx.all = K, b, tol, solve_all_labels
+        return prob
+
+    @staticmethod
+    def backward(ctx, grad_prob):
+        g, labels, prob = ctx.saved_tensors
+        K = ctx.K
+        grad_g = torch.zeros_like(g, dtype=torch.float64)
+        grad_b = 0.0
+        solved = range(1, K + 1) if ctx.all else range(2, K + 1)
+        for s in solved:
+            gs = grad_prob[s - 1] if ctx.all else grad_prob[s - 1] - grad_prob[0]
+            if not torch.any(gs != 0):
+                continue
+            dg, db = solve_backward(g.contiguous(), labels, K, ctx.beta, s, prob[s - 1], gs,
+                                    tol=min(ctx.tol, 1e-10))
+            grad_g += dg
+            grad_b += db
+        gb = torch.tensor(grad_b, dtype=torch.float64, device=g.device)
+        return grad_g.to(g.dtype), gb, None, None, None, None
+
+
+def random_walker(g, beta, labels, K, tol=1e-10, solve_all_labels=False):
+    """Differentiable probabilities [K][grid] (see RandomWalkerFn)."""
+    if not torch.is_tensor(beta):
+        beta = torch.tensor(float(beta), dtype=torch.float64, device=g.device)
+    return RandomWalkerFn.apply(g, beta, labels, K, tol, solve_all_labels)

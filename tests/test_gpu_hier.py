@@ -1,0 +1,165 @@
+"""GPU parity of the coarse-to-fine pieces against the oracle: LOD step,
+coarse seeds, brick classification, upsampled fill, batched brick solves and
+the whole hierarchical pipeline."""
+import numpy as np
+import pytest
+
+from oracle import rw_oracle as O
+from synth import blob_case
+from tests._helpers import assert_parity, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rw():
+    from paper_2509_26213_amd import rw as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def case():
+    # ragged sizes (not multiples of the brick or of 4), three labels, u16
+    return blob_case(shape=(45, 52, 70), n_blobs=6, K=3, seeds_per_label=40, sigma=0.06,
+                     rmin=5, rmax=14, seed=31, dtype="u16")
+
+
+@pytest.fixture(scope="module")
+def coarse_ref(case):
+    """Oracle levels and coarse solution (float64), the GPU brick stage's input."""
+    g = O.case_g(case)
+    g1, l1 = O.downsample_mean(g), O.coarse_seeds(case.labels)
+    g2, l2 = O.downsample_mean(g1), O.coarse_seeds(l1)
+    coarse = O.random_walker(g2, l2, case.K, case.beta, method="pcg", tol=1e-10)
+    return g, (g1, l1), (g2, l2), coarse
+
+
+def test_downsample_matches_oracle(rw, case, coarse_ref):
+    import torch
+    g, (g1, l1), (g2, l2), _ = coarse_ref
+    vol, lab = dev(case.vol), dev(case.labels)
+    d1, dl1 = rw.downsample(vol, lab, out_dtype=torch.float64)
+    d2, dl2 = rw.downsample(d1, dl1, lo=0.0, hi=1.0, out_dtype=torch.float64)
+    assert np.allclose(host(d1), g1, rtol=0, atol=1e-15)
+    assert np.allclose(host(d2), g2, rtol=0, atol=1e-15)
+    assert np.array_equal(host(dl1), l1) and np.array_equal(host(dl2), l2)
+    f32, _ = rw.downsample(vol, None, out_dtype=torch.float32)
+    assert np.allclose(host(f32), g1, rtol=1e-6, atol=1e-7)
+
+
+def _up(coarse, shape, f, origin, size):
+    return np.stack([O.upsample_trilinear(coarse[k], shape, f, (origin, size))
+                     for k in range(coarse.shape[0])])
+
+
+@pytest.mark.parametrize("offset", [(0, 0, 0), (5, 3, 7)])
+def test_classify_matches_oracle(rw, case, coarse_ref, offset):
+    _, _, _, coarse = coarse_ref
+    brick = (16, 16, 16)
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, brick, offset)
+    ref = O.brick_grid(case.shape, brick, offset)
+    assert [tuple(map(tuple, b)) for b in cands] == [(tuple(o), tuple(s)) for o, s in ref]
+    for (o, s), a in zip(ref, active):
+        P = _up(coarse, case.shape, 4, tuple(np.array(o) - 1), tuple(np.array(s) + 2))
+        assert O.classify_brick(P, case.labels, case.shape, o, s) == a, (o, s)
+    assert 0 < sum(active) < len(active)
+
+
+def test_fill_matches_upsampling(rw, case, coarse_ref):
+    import torch
+    _, _, _, coarse = coarse_ref
+    bricks = O.brick_grid(case.shape, (16, 16, 16), (0, 0, 0))[::3]
+    prob = torch.full((3,) + case.shape, -1.0, dtype=torch.float32, device="cuda")
+    rw.fill_bricks(dev(coarse), dev(case.labels), 4, bricks, prob)
+    P = host(prob)
+    for o, s in bricks:
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        ref = _up(coarse, case.shape, 4, o, s)
+        lab = case.labels[sl]
+        for k in range(3):
+            r = ref[k].copy()
+            r[lab > 0] = (lab[lab > 0] == k + 1)
+            assert np.allclose(P[k][sl], r, atol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_brick_solves_match_oracle(rw, case, coarse_ref, precision):
+    g, _, _, coarse = coarse_ref
+    offset = (5, 3, 7)
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, (16, 16, 16), offset)
+    act = [b for b, a in zip(cands, active) if a][:12]
+    prob, iters, st = rw.solve_bricks(dev(case.vol), dev(case.labels), 3, case.beta, dev(coarse), 4,
+                                      act, tol=1e-6, precision=precision, return_stats=True)
+    P = host(prob)
+    assert st["status"] == 0
+    for (o, s), it in zip(act, iters):
+        o, s = tuple(o), tuple(s)
+        Pf = _up(coarse, case.shape, 4, tuple(np.array(o) - 1), tuple(np.array(s) + 2))
+
+        def shell_value(lab, zz, yy, xx, Pf=Pf, o=o):
+            return Pf[lab - 1][zz - o[0] + 1, yy - o[1] + 1, xx - o[2] + 1]
+
+        x0 = Pf[:, 1:-1, 1:-1, 1:-1]
+        xb, info = O.solve_brick(g, case.labels, o, s, shell_value, x0, case.beta, tol=1e-6)
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        assert_parity(P[:, sl[0], sl[1], sl[2]], xb, what=f"brick {o} {precision}")
+        if precision == "fp64":
+            # same algorithm, same x0, same stopping rule: the same count +- 1
+            for r in range(2):
+                assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
+
+
+def test_bricks_untouched_outside(rw, case, coarse_ref):
+    import torch
+    _, _, _, coarse = coarse_ref
+    b = [((0, 0, 0), (16, 20, 24))]
+    prob = torch.full((3,) + case.shape, 7.0, dtype=torch.float32, device="cuda")
+    rw.solve_bricks(dev(case.vol), dev(case.labels), 3, case.beta, dev(coarse), 4, b,
+                    prob_out=prob, precision="mixed")
+    P = host(prob)
+    inside = np.zeros(case.shape, bool)
+    inside[:16, :20, :24] = True
+    assert np.all(P[:, ~inside] == 7.0)
+    assert np.all(P[:, inside] != 7.0)
+
+
+def test_hierarchical_coarse_tolerance_induced_gap(rw, case, coarse_ref):
+    """At tol 1e-6 this coarse grid is ill-conditioned enough that a
+    tolerance-stopped solve is 3e-3 away from the exact solution, so the
+    complement background differs from an independent background solve by
+    that much.  The solved labels (2, 3) follow the oracle's PCG run."""
+    import torch
+    g, _, (g2, l2), _ = coarse_ref
+    xs = O.random_walker(g2, l2, 3, case.beta, method="pcg", tol=1e-6)
+    xe = O.random_walker(g2, l2, 3, case.beta, method="direct")
+    assert np.max(np.abs(xs - xe)) > 1e-5          # the disclosed gap
+    prob, _ = rw.solve(dev(g2), dev(l2), 3, case.beta, tol=1e-6, precision="fp64", lo=0.0, hi=1.0)
+    assert np.max(np.abs(host(prob)[1:] - xs[1:])) < 1e-5
+
+
+@pytest.mark.parametrize("brick_precision", ["mixed", "fp64"])
+def test_hierarchical_pipeline_matches_oracle(rw, case, brick_precision):
+    """End to end at tol 1e-9 (the second parity run for a tolerance-induced
+    gap): the oracle runs its own levels, coarse solve and brick list; brick
+    lists agree except for bricks within 1e-4 of a threshold, probabilities
+    agree to 1e-5 on the agreeing bricks."""
+    g = O.case_g(case)
+    brick, offset = (16, 16, 16), (5, 3, 7)
+    ref = O.hierarchical_rw(g, case.labels, 3, case.beta, levels=2, brick=brick, offset=offset,
+                            tol=1e-9)
+    prob, info = rw.hierarchical_solve(dev(case.vol), dev(case.labels), 3, case.beta, levels=2,
+                                       brick=brick, offset=offset, tol=1e-9,
+                                       coarse_precision="fp64", brick_precision=brick_precision,
+                                       return_info=True)
+    P = host(prob)
+    assert np.max(np.abs(host(info["coarse"]) - ref["coarse"])) < 1e-5
+    diff = [i for i, (a, b) in enumerate(zip(info["active"], ref["active"])) if a != b]
+    assert len(diff) <= 2, diff
+    assert sum(ref["active"]) >= 5
+    for i, ((o, s), a) in enumerate(zip(ref["bricks"], ref["active"])):
+        if i in diff:
+            continue
+        sl = tuple(slice(x, x + y) for x, y in zip(o, s))
+        assert_parity(P[:, sl[0], sl[1], sl[2]], ref["prob"][:, sl[0], sl[1], sl[2]],
+                      what=f"brick {o}")
