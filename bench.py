@@ -48,6 +48,10 @@ def pass_bytes(n_vox, launches, rhs_iterations, s_g, s_m, s_v, which):
 
 def make_workload(name):
     from synth import blob_case
+    if name == "hier1024":
+        return blob_case(shape=(1024, 1024, 1024), n_blobs=256, K=3, seeds_per_label=8000,
+                         sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3,
+                         dtype="u16", name="hier1024")
     if name == "blob512":
         return blob_case(shape=(512, 512, 512), n_blobs=32, K=3, seeds_per_label=1000,
                          sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=2,
@@ -57,6 +61,49 @@ def make_workload(name):
                          sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=2,
                          dtype="f32", name="blob256")
     raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    """sha256 of the stencil kernel source (the traffic counters are only
+    quoted while it is unchanged)."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2509_26213_amd", "csrc", "rw_cg_kernels.h")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/<kernel>_<workload>_traffic.md), or None when it is missing or
+    was taken on another version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters: 1 GiB read + 1 GiB written per launch, 5 launches."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
 
 
 def cpu_baseline(case, gpu_iters_fp64, n_iter, threads):
@@ -92,7 +139,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="profiling runs only: cap CG iterations (the JSON line is then not a "
+                         "whole solve)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -103,6 +158,8 @@ def main():
     from paper_2509_26213_amd import rw
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "hier1024":
+        return bench_hier(args)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     case = make_workload(args.workload)
@@ -116,10 +173,17 @@ def main():
     ws = torch.empty(rw.solve_workspace_bytes(case.shape, K, "fp64"), dtype=torch.uint8,
                      device=dev)
 
+    extra = {"max_iter": args.profile_iters} if args.profile_iters else {}
+
     def step(precision, timing):
+        import warnings
         lo, hi = rw.minmax(vol, ctx=ctx)
-        return rw.solve(vol, lab, K, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
-                        ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing)
+        with warnings.catch_warnings():
+            if args.profile_iters:
+                warnings.simplefilter("ignore")
+            return rw.solve(vol, lab, K, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
+                            ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing,
+                            **extra)
 
     def timed(precision, steps, warmup):
         for _ in range(warmup):
@@ -177,7 +241,7 @@ def main():
                    "voxels": n_vox, "labels": K, "solved_labels": s["num_solved"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass2", "achieved": ach2,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": measured_traffic("k_cg_pass2", case.name),
                      "avg_launch_us": ms2 * 1e3 / max(launches2, 1),
                      "bytes_per_launch": bytes2 / max(launches2, 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
@@ -199,6 +263,86 @@ def main():
         except Exception as e:  # the baseline never hides the GPU result
             result["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)
+
+
+def bench_hier(args):
+    """Hierarchical workload (1024^3 u16): levels 1, 2 by device LOD steps,
+    the 256^3 level solved whole (mixed), 64^3 bricks on a grid offset
+    (48, 20, 40) classified from the upsampled coarse solution, the uncertain
+    ones solved in one batched brick solve (mixed), the others filled.  One
+    step = the whole pipeline on the resident volume."""
+    import numpy as np
+    import torch
+    from paper_2509_26213_amd import rw
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    case = make_workload("hier1024")
+    print(f"# workload {case.name} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    vol = torch.from_numpy(case.vol).to(dev)
+    lab = torch.from_numpy(case.labels).to(dev)
+    del case.vol
+    K, n_vox = case.K, int(np.prod(case.shape))
+    brick, offset = (64, 64, 64), (48, 20, 40)
+
+    def step():
+        g1, l1 = rw.downsample(vol, lab, out_dtype=torch.float32)
+        g2, l2 = rw.downsample(g1, l1, lo=0.0, hi=1.0, out_dtype=torch.float32)
+        coarse, _, cst = rw.solve(g2, l2, K, case.beta, tol=1e-6, precision="mixed", lo=0.0,
+                                  hi=1.0, argmax=False, return_stats=True)
+        cands, active = rw.classify_bricks(coarse, lab, 4, brick, offset)
+        act = [b for b, a in zip(cands, active) if a]
+        ina = [b for b, a in zip(cands, active) if not a]
+        prob = torch.empty((K,) + tuple(vol.shape), dtype=torch.float32, device=dev)
+        if ina:
+            rw.fill_bricks(coarse, lab, 4, ina, prob)
+        t = time.perf_counter()
+        _, iters, bst = rw.solve_bricks(vol, lab, K, case.beta, coarse, 4, act, prob_out=prob,
+                                        tol=1e-6, precision="mixed", return_stats=True,
+                                        kernel_timing=True, lo=0.0, hi=65535.0)
+        torch.cuda.synchronize()
+        return dict(coarse=cst, bricks=bst, n_active=len(act), n_cand=len(cands),
+                    brick_s=time.perf_counter() - t, iters=iters)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / args.steps
+    o = outs[-1]
+    b = o["bricks"]
+    bytes2 = b["box_voxel_iterations"] * (2 + 1) + 5 * 4 * b["rhs_voxel_iterations"]
+    bytes1 = b["box_voxel_iterations"] * 2 + 3 * 4 * b["rhs_voxel_iterations"]
+    ach2 = bytes2 / (b["pass_ms"][1] * 1e-3) / 1e9
+    ach1 = bytes1 / (b["pass_ms"][0] * 1e-3) / 1e9
+    act_vox = b["unknowns"]
+    its = np.array(o["iters"])
+    print(json.dumps({
+        "metric": METRIC, "value": n_vox / sec, "unit": "voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64dot", "data": "synthetic",
+        "config": {"workload": "hier1024: 1024^3 uint16 blob volume (256 blobs, 8000 seeds per "
+                               "label, K=3, beta 150), level-2 256^3 solved whole, 64^3 bricks on "
+                               "offset grid, uncertain bricks solved batched, mixed, tol 1e-6",
+                   "voxels": n_vox, "candidate_bricks": o["n_cand"],
+                   "active_bricks": o["n_active"]},
+        "bricks": {"voxels_per_s": act_vox / (b["device_ms"] * 1e-3),
+                   "device_ms": b["device_ms"], "loop_ms": b["loop_ms"],
+                   "iters_median": float(np.median(its)) if its.size else 0,
+                   "iters_max": int(its.max()) if its.size else 0,
+                   "refreshes": b["refinements"]},
+        "roofline": {"bound": "hbm", "kernel": "k_cg_pass2 (bricks)", "achieved": ach2,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_cg_pass2", "hier1024"),
+                     "avg_launch_us": b["pass_ms"][1] * 1e3 / max(b["pass_launches"][1], 1)},
+        "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
+        "stencil_cg_loop_frac": (bytes1 + bytes2) / ((b["pass_ms"][0] + b["pass_ms"][1]) * 1e-3)
+        / 1e9 / HBM_PEAK_GBS,
+        "coarse": {"iters": o["coarse"]["iters"], "device_ms": o["coarse"]["device_ms"]},
+    }), flush=True)
 
 
 if __name__ == "__main__":

@@ -132,10 +132,23 @@ typedef struct {
     int64_t unknowns;                    /* unseeded voxels solved for */
 } rw_stats;
 
-/* Fine-level brick: origin and size in voxels of the fine grid. */
+/* Fine-level brick: origin and size in voxels of the fine grid (or of its
+ * sub-volume, see rw_subvolume). */
 typedef struct {
     int32_t ox, oy, oz, sx, sy, sz;
 } rw_brick;
+
+/* A brick's own volume in a pool (streamed solves): a box of the fine grid
+ * stored contiguously, C order, starting at element `offset` of the pool's
+ * intensity, label and output arrays; (gx, gy, gz) is the global fine
+ * position of its origin.  Its faces are the volume's faces for the solver
+ * (no edge leaves it), so a brick with a one-voxel halo on every side that
+ * is inside the global volume sees exactly its global neighbourhood. */
+typedef struct {
+    int64_t offset;
+    int32_t nx, ny, nz;
+    int32_t gx, gy, gz;
+} rw_subvolume;
 
 typedef struct rw_context rw_context;
 
@@ -222,27 +235,35 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
  * probability).  x0 = the upsampled coarse probabilities; stopping
  * ||r|| <= tol ||b|| per brick and label (b of the brick system).
  * Precision MIXED (float32 CG, float64 dots, float64 residual refreshes) or
- * FP64; opts->x0 is ignored.  Bricks need not be disjoint from seeds; they
- * must lie inside the volume.
- * bricks: host array of n_bricks.  prob_out: [K][nz][ny][nx] float32 fine
- *   grid: the voxels of the bricks are overwritten, other voxels untouched.
+ * FP64; opts->x0 is ignored.  Bricks must lie inside their volume.
+ * bricks: host array of n_bricks.
+ * subvols: NULL (every brick lies in `fine`), or host array of n_bricks: brick
+ *   i lies in sub-volume i of the pool `fine` (its data and labels, with
+ *   fine->dims the pool's total size as (n, 1, 1)); coarse upsampling uses
+ *   global positions.
+ * prob_out: [K][voxels of `fine`] float32: the voxels of the bricks are
+ *   overwritten (at their pool positions), other voxels untouched.
  * brick_iters: NULL or host int32 [n_bricks][R] CG iterations per brick/label.
  * ws: rw_bricks_workspace_bytes(...). */
 size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32_t num_labels,
                                  int32_t precision, int32_t solve_all_labels);
 rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* fine_seeds,
                           const void* coarse_prob, int32_t coarse_dtype, rw_dims coarse_dims,
-                          int32_t factor, const rw_brick* bricks, int32_t n_bricks,
-                          const rw_options* opts, float* prob_out, int32_t* brick_iters,
-                          void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
+                          int32_t factor, const rw_brick* bricks, const rw_subvolume* subvols,
+                          int32_t n_bricks, const rw_options* opts, float* prob_out,
+                          int32_t* brick_iters, void* ws, size_t ws_bytes, rw_stats* stats,
+                          void* stream);
 
 /* Upsampled coarse probabilities written into the fine grid for every voxel
- * of the listed bricks (the inactive ones), seeds exact.  prob_out: [K][fine]
- * float32. */
+ * of the listed bricks (the inactive ones), seeds exact.  prob_out: [K][voxels
+ * of the label array] float32.  subvols: as for rw_solve_bricks (NULL: the
+ * bricks lie in the fine grid of fine_dims; else fine_dims is the pool size
+ * as (n, 1, 1) and brick i lies in sub-volume i). */
 rw_status rw_fill_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
                          rw_dims coarse_dims, int32_t num_labels, int32_t factor,
                          const uint8_t* fine_labels, rw_dims fine_dims, const rw_brick* bricks,
-                         int32_t n_bricks, float* prob_out, void* stream);
+                         const rw_subvolume* subvols, int32_t n_bricks, float* prob_out,
+                         void* stream);
 
 /* Adjoint gradient of a loss L(x^s) of one solved label s (float64).
  * x_full: [nz][ny][nx] the forward solution of label s (seeds exact).

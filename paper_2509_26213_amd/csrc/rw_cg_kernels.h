@@ -24,6 +24,9 @@ namespace rw {
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 struct BoxTile {
+    Geom G;                  // the volume the box lives in
+    int64_t voff;            // offset of that volume in the intensity / label arrays
+    int gox, goy, goz;       // global position of that volume's origin (coarse upsampling)
     int ox, oy, oz;          // box origin in the volume
     int sx, sy, sz;          // box size
     int X0, Y0, z0, z1;      // tile origin (box-local) and plane range [z0, z1)
@@ -41,6 +44,9 @@ struct WholeTiles {
         const int t = tm.tile(i);
         if (t < 0) return false;
         const int tx = t % tm.gx, ty = (t / tm.gx) % tm.gy, tz = t / (tm.gx * tm.gy);
+        b.G = G;
+        b.voff = 0;
+        b.gox = b.goy = b.goz = 0;
         b.ox = b.oy = b.oz = 0;
         b.sx = G.nx;
         b.sy = G.ny;
@@ -57,8 +63,12 @@ struct WholeTiles {
     }
 };
 
-// One brick of a batched solve.
+// One brick of a batched solve: the box inside its volume, and that volume
+// (the whole fine grid, or the brick's own sub-volume in a pool).
 struct BrickGeo {
+    int vnx, vny, vnz;   // volume dims
+    int gox, goy, goz;   // global position of the volume's origin
+    int64_t vvoff;       // offset of the volume in the intensity / label arrays
     int ox, oy, oz, sx, sy, sz;
     int gx, gy;         // tiles per row of columns / per column of rows
     int tile0, ntiles;  // its tiles in the global tile table
@@ -80,6 +90,15 @@ struct BrickTiles {
         const BrickGeo B = bricks[bi];
         const int t = g - B.tile0;
         const int tx = t % B.gx, ty = (t / B.gx) % B.gy, tz = t / (B.gx * B.gy);
+        b.G.nx = B.vnx;
+        b.G.ny = B.vny;
+        b.G.nz = B.vnz;
+        b.G.plane = (int64_t)B.vnx * B.vny;
+        b.G.n = b.G.plane * B.vnz;
+        b.voff = B.vvoff;
+        b.gox = B.gox;
+        b.goy = B.goy;
+        b.goz = B.goz;
         b.ox = B.ox;
         b.oy = B.oy;
         b.oz = B.oz;
@@ -163,7 +182,7 @@ __device__ __forceinline__ double upsample(const Shell& s, int label, int x, int
 // refreshes z of the labels flagged for it (st.outer_active == 2).
 template <typename V, typename T, int R, int BY, typename TS>
 __global__ __launch_bounds__(64 * BY) void k_residual(
-    const V* __restrict__ vol, const uint8_t* __restrict__ lab, Geom G, WCoef wc, TS ts,
+    const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     Shell sh, int lab0, const double* __restrict__ x64, const double* __restrict__ rhs,
     T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
     const RhsState* __restrict__ st, double* __restrict__ part) {
@@ -172,6 +191,9 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
         if (!ts.get(it, bt)) continue;
+        const Geom& G = bt.G;
+        const V* __restrict__ vol = volp + bt.voff;
+        const uint8_t* __restrict__ lab = labp + bt.voff;
         int wmask = 0;
         if (mode == 2) {
 #pragma unroll
@@ -259,7 +281,8 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                             xj = x64 ? x64[vb + nbb[k]] : 0.0;
                         } else {
                             xj = (sh.coarse && lab0 > 0)
-                                     ? upsample(sh, L, gx + dxl[k], gy + dyl[k], gz + dzl[k])
+                                     ? upsample(sh, L, bt.gox + gx + dxl[k], bt.goy + gy + dyl[k],
+                                                bt.goz + gz + dzl[k])
                                      : 0.0;
                             b += w[k] * xj;
                         }
@@ -383,7 +406,7 @@ __device__ __forceinline__ int box_labels(const RhsState* __restrict__ st, int s
 // writes p_new to the other one.  qout (optional) receives q.
 template <typename V, typename T, int R, int BY, int U, typename TS>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
-    const V* __restrict__ vol, Geom G, WCoef wc, TS ts, const T* __restrict__ zv,
+    const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
     const RhsState* __restrict__ st, double* __restrict__ part) {
     constexpr int NYH = TileLanes<BY, U>::NYH;
@@ -396,6 +419,8 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
         bool act[R];
         int src[R];
         if (box_labels<R>(st, bt.sidx, act, src) < 0) continue;  // uniform over the block
+        const Geom& G = bt.G;
+        const V* __restrict__ vol = volp + bt.voff;
         T bet[R];
         const T* zr[R];
         const T* po[R];
@@ -546,7 +571,7 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 // ([2R][ntiles]).
 template <typename V, typename T, int R, int BY, int U, typename TS>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
-    const V* __restrict__ vol, const uint8_t* __restrict__ lab, Geom G, WCoef wc, TS ts,
+    const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
     const T* __restrict__ pb1, const RhsState* __restrict__ st, double* __restrict__ part) {
     constexpr int NYH = TileLanes<BY, U>::NYH;
@@ -559,6 +584,9 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
         bool act[R];
         int src[R];
         if (box_labels<R>(st, bt.sidx, act, src) < 0) continue;
+        const Geom& G = bt.G;
+        const V* __restrict__ vol = volp + bt.voff;
+        const uint8_t* __restrict__ lab = labp + bt.voff;
         T alp[R];
         const T* pr[R];
         const T* xr[R];

@@ -61,7 +61,10 @@ __global__ __launch_bounds__(256) void k_downsample(const V* __restrict__ vol, G
 // ================================================================== classify / fill
 
 struct DevBrick {
-    int ox, oy, oz, sx, sy, sz;
+    int ox, oy, oz, sx, sy, sz;     // box in its volume
+    int vnx, vny;                   // its volume's row / plane sizes
+    int gox, goy, goz;              // global position of the volume's origin
+    int64_t voff;                   // offset of the volume in the label / output arrays
 };
 
 // One block per candidate brick; flags[b] = 1 if active.
@@ -131,23 +134,27 @@ __global__ __launch_bounds__(256) void k_classify(Shell sh, int K, Geom F,
     if (threadIdx.x == 0) flags[blockIdx.x] = found ? 1 : 0;
 }
 
-// Upsampled probabilities (seeds exact) for every voxel of the listed bricks.
-__global__ __launch_bounds__(256) void k_fill(Shell sh, int K, Geom F,
+// Upsampled probabilities (seeds exact) for every voxel of the listed bricks
+// (each in its volume; n = voxels of the label / output arrays).
+__global__ __launch_bounds__(256) void k_fill(Shell sh, int K, int64_t n,
                                               const uint8_t* __restrict__ lab,
                                               const DevBrick* __restrict__ bricks,
                                               float* __restrict__ prob) {
     const DevBrick b = bricks[blockIdx.y];
     const int64_t inner = (int64_t)b.sx * b.sy * b.sz;
     const int64_t fxy = (int64_t)b.sx * b.sy;
+    const int64_t plane = (int64_t)b.vnx * b.vny;
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < inner; i += 256ll * gridDim.x) {
         const int z = b.oz + int(i / fxy);
         const int64_t r = i % fxy;
         const int y = b.oy + int(r / b.sx);
         const int x = b.ox + int(r % b.sx);
-        const int64_t g = (int64_t)z * F.plane + (int64_t)y * F.nx + x;
+        const int64_t g = b.voff + (int64_t)z * plane + (int64_t)y * b.vnx + x;
         const uint8_t l = lab[g];
         for (int L = 1; L <= K; ++L)
-            prob[(int64_t)(L - 1) * F.n + g] = l ? (l == L ? 1.f : 0.f) : (float)upsample(sh, L, x, y, z);
+            prob[(int64_t)(L - 1) * n + g] =
+                l ? (l == L ? 1.f : 0.f)
+                  : (float)upsample(sh, L, b.gox + x, b.goy + y, b.goz + z);
     }
 }
 
@@ -418,7 +425,7 @@ __global__ __launch_bounds__(1024) void k_compact(const BrickGeo* __restrict__ g
 
 // x64 = upsampled coarse value on the unknowns of the boxes, xi = 0.
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Geom F, Shell sh, int lab0,
+__global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Shell sh, int lab0,
                                                     const uint8_t* __restrict__ lab,
                                                     double* __restrict__ x64, T* __restrict__ xi) {
     const int cnt = ts.count();
@@ -431,11 +438,11 @@ __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Geom F, Shell
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
                 const int gx = bt.ox + lxb, gy = bt.oy + yy, gz = bt.oz + lz;
                 const int64_t cb = ((int64_t)lz * bt.sy + yy) * bt.sx + lxb;
-                const uint8_t l = lab[(int64_t)gz * F.plane + (int64_t)gy * F.nx + gx];
+                const uint8_t l = lab[bt.voff + (int64_t)gz * bt.G.plane + (int64_t)gy * bt.G.nx + gx];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int64_t o = bt.vbase + r * bt.vstride + cb;
-                    x64[o] = l ? 0.0 : upsample(sh, lab0 + r, gx, gy, gz);
+                    x64[o] = l ? 0.0 : upsample(sh, lab0 + r, bt.gox + gx, bt.goy + gy, bt.goz + gz);
                     if (xi) xi[o] = T(0);
                 }
             }
@@ -446,7 +453,7 @@ __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Geom F, Shell
 // x64 += xi, xi = 0 on the unknowns of the listed tiles, for the labels
 // flagged for a refresh (all labels when all = 1).
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts, Geom F,
+__global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts,
                                                     const uint8_t* __restrict__ lab,
                                                     const RhsState* __restrict__ st,
                                                     double* __restrict__ x64, T* __restrict__ xi,
@@ -464,8 +471,8 @@ __global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts, Geom F,
         for (int yy = bt.Y0 + (threadIdx.x >> 6); yy < min(bt.Y0 + ts.by, bt.sy); yy += 4) {
             if (lxb >= bt.sx) break;
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
-                const int64_t g = (int64_t)(bt.oz + lz) * F.plane + (int64_t)(bt.oy + yy) * F.nx +
-                                  bt.ox + lxb;
+                const int64_t g = bt.voff + (int64_t)(bt.oz + lz) * bt.G.plane +
+                                  (int64_t)(bt.oy + yy) * bt.G.nx + bt.ox + lxb;
                 if (lab[g]) continue;
                 const int64_t cb = ((int64_t)lz * bt.sy + yy) * bt.sx + lxb;
 #pragma unroll
@@ -496,8 +503,8 @@ __global__ __launch_bounds__(256) void k_brick_write(BrickTiles ts, Geom F,
         for (int yy = bt.Y0 + (threadIdx.x >> 6); yy < min(bt.Y0 + ts.by, bt.sy); yy += 4) {
             if (lxb >= bt.sx) break;
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
-                const int64_t g = (int64_t)(bt.oz + lz) * F.plane + (int64_t)(bt.oy + yy) * F.nx +
-                                  bt.ox + lxb;
+                const int64_t g = bt.voff + (int64_t)(bt.oz + lz) * bt.G.plane +
+                                  (int64_t)(bt.oy + yy) * bt.G.nx + bt.ox + lxb;
                 const int64_t cb = ((int64_t)lz * bt.sy + yy) * bt.sx + lxb;
                 const uint8_t l = lab[g];
                 double s = 0.0;
@@ -523,7 +530,8 @@ struct BrickPlan {
 };
 
 // Bricks sorted by decreasing size (stable), tiles of 64 x by x zc.
-static BrickPlan make_plan(const rw_brick* bricks, int n, int R, int by, int zc) {
+static BrickPlan make_plan(const rw_brick* bricks, int n, int R, int by, int zc,
+                           const rw_subvolume* sub = nullptr, rw_dims vol = rw_dims{1, 1, 1}) {
     BrickPlan P;
     P.order.resize(n);
     for (int i = 0; i < n; ++i) P.order[i] = i;
@@ -535,6 +543,22 @@ static BrickPlan make_plan(const rw_brick* bricks, int n, int R, int by, int zc)
     for (int i = 0; i < n; ++i) {
         const rw_brick& b = bricks[P.order[i]];
         BrickGeo g;
+        if (sub) {
+            const rw_subvolume& v = sub[P.order[i]];
+            g.vnx = v.nx;
+            g.vny = v.ny;
+            g.vnz = v.nz;
+            g.gox = v.gx;
+            g.goy = v.gy;
+            g.goz = v.gz;
+            g.vvoff = v.offset;
+        } else {
+            g.vnx = int(vol.nx);
+            g.vny = int(vol.ny);
+            g.vnz = int(vol.nz);
+            g.gox = g.goy = g.goz = 0;
+            g.vvoff = 0;
+        }
         g.ox = b.ox;
         g.oy = b.oy;
         g.oz = b.oz;
@@ -683,13 +707,13 @@ struct BrickSolve {
         const BrickTiles ta = act();
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
         hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, BrickTiles>), dim3(grid), dim3(64, BY), 0,
-                           s, vol, F, wc, ta, (const T*)B.z, (T*)B.p0, (T*)B.p1, (T*)nullptr, B.st,
+                           s, vol, wc, ta, (const T*)B.z, (T*)B.p0, (T*)B.p1, (T*)nullptr, B.st,
                            B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_bfin1<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
         hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, BrickTiles>), dim3(grid), dim3(64, BY), 0,
-                           s, vol, lab, F, wc, ta, mixed ? (T*)B.xi : (T*)B.x64, (T*)B.z,
+                           s, vol, lab, wc, ta, mixed ? (T*)B.xi : (T*)B.x64, (T*)B.z,
                            (const T*)B.p0, (const T*)B.p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
         hipLaunchKernelGGL((k_bfin2<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st,
@@ -701,10 +725,10 @@ struct BrickSolve {
     rw_status refresh() {
         hipStream_t s = ctx->s;
         const BrickTiles tr = ref();
-        hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, F, lab, B.st,
+        hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, lab, B.st,
                            B.x64, (T*)B.xi, 0);
         hipLaunchKernelGGL((k_residual<V, T, R, BY, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
-                           vol, lab, F, wc, tr, sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
+                           vol, lab, wc, tr, sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, (T*)B.xi, 2, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_refresh<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo,
                            B.st, o->tol);
@@ -725,10 +749,10 @@ struct BrickSolve {
                               hipMemcpyHostToDevice, s));
         RW_HIP(hipMemcpyAsync(B.counts, cnt_all, sizeof(cnt_all), hipMemcpyHostToDevice, s));
         // x0 = upsampled coarse solution, then the brick residuals
-        hipLaunchKernelGGL((k_brick_init<T, R>), dim3(grid), dim3(256), 0, s, all(), F, sh, lab0, lab,
+        hipLaunchKernelGGL((k_brick_init<T, R>), dim3(grid), dim3(256), 0, s, all(), sh, lab0, lab,
                            B.x64, mixed ? (T*)B.xi : (T*)nullptr);
         hipLaunchKernelGGL((k_residual<V, T, R, BY, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
-                           vol, lab, F, wc, all(), sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
+                           vol, lab, wc, all(), sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, mixed ? (T*)B.xi : (T*)nullptr, 1, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_init<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st,
                            o->tol, o->max_iter);
@@ -801,7 +825,7 @@ struct BrickSolve {
         if (e) return e;
         RW_HIP(e2);
         if (mixed)
-            hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, all(), F, lab, B.st,
+            hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, all(), lab, B.st,
                                B.x64, (T*)B.xi, 1);
         RW_HIP(hipGetLastError());
         return RW_OK;
@@ -810,13 +834,14 @@ struct BrickSolve {
 
 template <typename V, typename T, int R, int BY>
 static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
-                            const Shell& sh, const rw_brick* bricks, int n_bricks,
+                            const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub,
+                            int n_bricks,
                             const rw_options* o, float* prob_out, int32_t* brick_iters, void* ws,
                             const TileChoice& tc, rw_stats* stats) {
     const bool mixed = o->precision == RW_PREC_MIXED;
     const int K = seeds->num_labels;
     const int lab0 = o->solve_all_labels ? 1 : 2;
-    BrickPlan P = make_plan(bricks, n_bricks, R, BY, tc.zc);
+    BrickPlan P = make_plan(bricks, n_bricks, R, BY, tc.zc, sub, fine->dims);
     BrickSolve<V, T, R, BY> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(fine->data);
@@ -877,22 +902,23 @@ static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_see
 
 template <typename V, typename T, int R>
 static rw_status bricks_by(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
-                           const Shell& sh, const rw_brick* bricks, int n, const rw_options* o,
-                           float* prob, int32_t* it, void* ws, rw_stats* st) {
+                           const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
+                           const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
     const TileChoice tc = brick_tiles(o->precision);
-    if (tc.by == 8) return bricks_run<V, T, R, 8>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, tc, st);
-    return bricks_run<V, T, R, 4>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, tc, st);
+    if (tc.by == 8)
+        return bricks_run<V, T, R, 8>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
+    return bricks_run<V, T, R, 4>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
 }
 
 template <typename V, typename T>
 static rw_status bricks_r(int R, rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
-                          const Shell& sh, const rw_brick* bricks, int n, const rw_options* o,
-                          float* prob, int32_t* it, void* ws, rw_stats* st) {
+                          const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
+                          const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
     switch (R) {
-        case 1: return bricks_by<V, T, 1>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, st);
-        case 2: return bricks_by<V, T, 2>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, st);
-        case 3: return bricks_by<V, T, 3>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, st);
-        case 4: return bricks_by<V, T, 4>(ctx, fine, seeds, sh, bricks, n, o, prob, it, ws, st);
+        case 1: return bricks_by<V, T, 1>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, st);
+        case 2: return bricks_by<V, T, 2>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, st);
+        case 3: return bricks_by<V, T, 3>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, st);
+        case 4: return bricks_by<V, T, 4>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, st);
     }
     set_error("brick solves support 1 to 4 solved labels");
     return RW_ERR_UNSUPPORTED;
@@ -964,7 +990,9 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
     cand.reserve(n);
     for (auto& z : cz)
         for (auto& y : cy)
-            for (auto& x : cx) cand.push_back(DevBrick{x.first, y.first, z.first, x.second, y.second, z.second});
+            for (auto& x : cx)
+                cand.push_back(DevBrick{x.first, y.first, z.first, x.second, y.second, z.second,
+                                        int(fine_dims.nx), int(fine_dims.ny), 0, 0, 0, 0});
     if ((e = ensure_dev_small(ctx, sizeof(DevBrick) * n + n + 256))) return e;
     if ((e = stream_enter(ctx, stream))) return e;
     DevBrick* dc = static_cast<DevBrick*>(ctx->dev_small);
@@ -982,6 +1010,9 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
     return stream_leave(ctx, stream);
 }
 
+static rw_status check_subvolumes(const rw_brick* bricks, const rw_subvolume* sub, int n,
+                                  rw_dims pool);
+
 static rw_status check_bricks(const rw_brick* bricks, int n, rw_dims d) {
     if (n < 0 || (n > 0 && !bricks)) return invalid("bad brick list");
     for (int i = 0; i < n; ++i) {
@@ -996,27 +1027,46 @@ static rw_status check_bricks(const rw_brick* bricks, int n, rw_dims d) {
 rw_status rw_fill_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
                          rw_dims coarse_dims, int32_t num_labels, int32_t factor,
                          const uint8_t* fine_labels, rw_dims fine_dims, const rw_brick* bricks,
-                         int32_t n_bricks, float* prob_out, void* stream) {
+                         const rw_subvolume* subvols, int32_t n_bricks, float* prob_out,
+                         void* stream) {
     if (!ctx || !fine_labels || !prob_out) return invalid("NULL argument");
     if (num_labels < 1 || num_labels > RW_MAX_LABELS) return invalid("num_labels must be in [1, 16]");
     Shell sh;
     rw_status e = make_shell(coarse_prob, coarse_dtype, coarse_dims, factor, &sh);
     if (e) return e;
-    if ((e = check_bricks(bricks, n_bricks, fine_dims))) return e;
+    if (n_bricks < 0 || (n_bricks > 0 && !bricks)) return invalid("bad brick list");
+    if (subvols) {
+        if ((e = check_subvolumes(bricks, subvols, n_bricks, fine_dims))) return e;
+    } else if ((e = check_bricks(bricks, n_bricks, fine_dims))) {
+        return e;
+    }
     if (n_bricks == 0) return RW_OK;
     if ((e = ensure_dev_small(ctx, sizeof(DevBrick) * size_t(n_bricks)))) return e;
     if ((e = stream_enter(ctx, stream))) return e;
     std::vector<DevBrick> v(n_bricks);
-    for (int i = 0; i < n_bricks; ++i)
-        v[i] = DevBrick{bricks[i].ox, bricks[i].oy, bricks[i].oz, bricks[i].sx, bricks[i].sy, bricks[i].sz};
+    for (int i = 0; i < n_bricks; ++i) {
+        const rw_brick& b = bricks[i];
+        DevBrick d{b.ox, b.oy, b.oz, b.sx, b.sy, b.sz, int(fine_dims.nx), int(fine_dims.ny), 0, 0, 0, 0};
+        if (subvols) {
+            const rw_subvolume& s = subvols[i];
+            d.vnx = s.nx;
+            d.vny = s.ny;
+            d.gox = s.gx;
+            d.goy = s.gy;
+            d.goz = s.gz;
+            d.voff = s.offset;
+        }
+        v[i] = d;
+    }
     DevBrick* db = static_cast<DevBrick*>(ctx->dev_small);
     RW_HIP(hipMemcpyAsync(db, v.data(), sizeof(DevBrick) * n_bricks, hipMemcpyHostToDevice, ctx->s));
     // the host vector must stay valid until the copy has run
     RW_HIP(hipStreamSynchronize(ctx->s));
+    const int64_t n = fine_dims.nx * fine_dims.ny * fine_dims.nz;
     for (int b0 = 0; b0 < n_bricks; b0 += 65535) {
         const int nb = std::min(65535, n_bricks - b0);
-        hipLaunchKernelGGL(k_fill, dim3(64, unsigned(nb)), dim3(256), 0, ctx->s, sh, num_labels,
-                           make_geom(fine_dims), fine_labels, db + b0, prob_out);
+        hipLaunchKernelGGL(k_fill, dim3(64, unsigned(nb)), dim3(256), 0, ctx->s, sh, num_labels, n,
+                           fine_labels, db + b0, prob_out);
     }
     RW_HIP(hipGetLastError());
     return stream_leave(ctx, stream);
@@ -1033,11 +1083,28 @@ size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32
     return carve_bricks(cv, P, R, precision == RW_PREC_MIXED, nullptr);
 }
 
+static rw_status check_subvolumes(const rw_brick* bricks, const rw_subvolume* sub, int n,
+                                  rw_dims pool) {
+    const int64_t total = pool.nx * pool.ny * pool.nz;
+    for (int i = 0; i < n; ++i) {
+        const rw_subvolume& v = sub[i];
+        if (v.nx < 1 || v.ny < 1 || v.nz < 1 || v.offset < 0 ||
+            v.offset + (int64_t)v.nx * v.ny * v.nz > total || v.gx < 0 || v.gy < 0 || v.gz < 0)
+            return invalid("sub-volume " + std::to_string(i) + " does not fit the pool");
+        const rw_brick& b = bricks[i];
+        if (b.sx < 1 || b.sy < 1 || b.sz < 1 || b.ox < 0 || b.oy < 0 || b.oz < 0 ||
+            b.ox + b.sx > v.nx || b.oy + b.sy > v.ny || b.oz + b.sz > v.nz)
+            return invalid("brick " + std::to_string(i) + " does not lie inside its sub-volume");
+    }
+    return RW_OK;
+}
+
 rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
                           const void* coarse_prob, int32_t coarse_dtype, rw_dims coarse_dims,
-                          int32_t factor, const rw_brick* bricks, int32_t n_bricks,
-                          const rw_options* o, float* prob_out, int32_t* brick_iters, void* ws,
-                          size_t ws_bytes, rw_stats* stats, void* stream) {
+                          int32_t factor, const rw_brick* bricks, const rw_subvolume* subvols,
+                          int32_t n_bricks, const rw_options* o, float* prob_out,
+                          int32_t* brick_iters, void* ws, size_t ws_bytes, rw_stats* stats,
+                          void* stream) {
     if (!ctx || !prob_out) return invalid("NULL argument");
     rw_status e = check_volume(fine);
     if (e) return e;
@@ -1052,7 +1119,12 @@ rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds
     }
     Shell sh;
     if ((e = make_shell(coarse_prob, coarse_dtype, coarse_dims, factor, &sh))) return e;
-    if ((e = check_bricks(bricks, n_bricks, fine->dims))) return e;
+    if (n_bricks < 0 || (n_bricks > 0 && !bricks)) return invalid("bad brick list");
+    if (subvols) {
+        if ((e = check_subvolumes(bricks, subvols, n_bricks, fine->dims))) return e;
+    } else if ((e = check_bricks(bricks, n_bricks, fine->dims))) {
+        return e;
+    }
     if (stats) memset(stats, 0, sizeof(*stats));
     if (n_bricks == 0) return RW_OK;
     const size_t need = rw_bricks_workspace_bytes(bricks, n_bricks, K, o->precision, o->solve_all_labels);
@@ -1072,21 +1144,21 @@ rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds
     const bool mixed = o->precision == RW_PREC_MIXED;
     switch (fine->dtype) {
         case RW_DT_U16:
-            e = mixed ? bricks_r<uint16_t, float>(R, ctx, fine, seeds, sh, bricks, n_bricks, o, prob_out,
+            e = mixed ? bricks_r<uint16_t, float>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o, prob_out,
                                                   brick_iters, ws, stats)
-                      : bricks_r<uint16_t, double>(R, ctx, fine, seeds, sh, bricks, n_bricks, o,
+                      : bricks_r<uint16_t, double>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o,
                                                    prob_out, brick_iters, ws, stats);
             break;
         case RW_DT_F32:
-            e = mixed ? bricks_r<float, float>(R, ctx, fine, seeds, sh, bricks, n_bricks, o, prob_out,
+            e = mixed ? bricks_r<float, float>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o, prob_out,
                                                brick_iters, ws, stats)
-                      : bricks_r<float, double>(R, ctx, fine, seeds, sh, bricks, n_bricks, o, prob_out,
+                      : bricks_r<float, double>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o, prob_out,
                                                 brick_iters, ws, stats);
             break;
         default:
-            e = mixed ? bricks_r<double, float>(R, ctx, fine, seeds, sh, bricks, n_bricks, o, prob_out,
+            e = mixed ? bricks_r<double, float>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o, prob_out,
                                                 brick_iters, ws, stats)
-                      : bricks_r<double, double>(R, ctx, fine, seeds, sh, bricks, n_bricks, o, prob_out,
+                      : bricks_r<double, double>(R, ctx, fine, seeds, sh, bricks, subvols, n_bricks, o, prob_out,
                                                  brick_iters, ws, stats);
     }
     RW_HIP(hipEventRecord(ctx->ev_end, ctx->s));

@@ -145,7 +145,7 @@ static rw_status apply_op_by(rw_context* ctx, const rw_volume* vol, const WCoef&
     ts.G = G;
     ts.ntiles = tm.tiles;
     hipLaunchKernelGGL((k_cg_pass1<V, T, 1, BY, PlaneBatch<T>::value, WholeTiles>),
-                       dim3(unsigned(tm.blocks())), dim3(64, BY), 0, ctx->s, (const V*)vol->data, G,
+                       dim3(unsigned(tm.blocks())), dim3(64, BY), 0, ctx->s, (const V*)vol->data,
                        wc, ts, (const T*)p, (T*)p, pnew, (T*)q, st, part);
     RW_HIP(hipGetLastError());
     RW_HIP(hipStreamSynchronize(ctx->s));

@@ -327,12 +327,12 @@ struct WholeSolve {
     rw_status launch_iteration(hipEvent_t* ev) {
         hipStream_t s = ctx->s;
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
-        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, G, wc, ts(), zv,
+        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, wc, ts(), zv,
                            p0, p1, (T*)nullptr, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_fin1<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, lab, G, wc, ts(),
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, lab, wc, ts(),
                            xv, zv, (const T*)p0, (const T*)p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
         hipLaunchKernelGGL((k_fin2<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st,
@@ -353,7 +353,7 @@ struct WholeSolve {
         Shell none;
         memset(&none, 0, sizeof(none));
         hipLaunchKernelGGL((k_residual<V, T, R, BY, WholeTiles>), grid(), block(), 0, ctx->s, vol, lab,
-                           G, wc, ts(), none, lab0, B.x64, rhs, zv, p0, p1,
+                           wc, ts(), none, lab0, B.x64, rhs, zv, p0, p1,
                            mixed ? (T*)B.xi : (T*)nullptr, mode, B.st, B.part);
         RW_HIP(hipGetLastError());
         return RW_OK;

@@ -95,6 +95,12 @@ class Stats(ctypes.Structure):
                     active_bricks=self.active_bricks, unknowns=self.unknowns)
 
 
+class SubVolume(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("gx", ctypes.c_int32), ("gy", ctypes.c_int32),
+                ("gz", ctypes.c_int32)]
+
+
 class Brick(ctypes.Structure):
     _fields_ = [("ox", ctypes.c_int32), ("oy", ctypes.c_int32), ("oz", ctypes.c_int32),
                 ("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("sz", ctypes.c_int32)]
@@ -138,10 +144,10 @@ def lib():
     L.rw_bricks_workspace_bytes.argtypes = [ctypes.POINTER(Brick), I32, I32, I32, I32]
     L.rw_bricks_workspace_bytes.restype = SZ
     L.rw_solve_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, I32, Dims,
-                                  I32, ctypes.POINTER(Brick), I32, ctypes.POINTER(Options), P,
-                                  P, P, SZ, ctypes.POINTER(Stats), P]
-    L.rw_fill_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(Brick), I32,
-                                 P, P]
+                                  I32, ctypes.POINTER(Brick), ctypes.POINTER(SubVolume), I32,
+                                  ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
+    L.rw_fill_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(Brick),
+                                 ctypes.POINTER(SubVolume), I32, P, P]
     L.rw_backward_workspace_bytes.argtypes = [Dims]
     L.rw_backward_workspace_bytes.restype = SZ
     L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
@@ -400,20 +406,34 @@ def classify_bricks(coarse_prob, labels, factor, brick=(64, 64, 64), offset=(0, 
     return [_from_brick(arr[i]) for i in range(n)], [bool(flags[i]) for i in range(n)]
 
 
-def fill_bricks(coarse_prob, labels, factor, bricks, prob_out, ctx=None):
+def _subvols_array(subvols, n):
+    if subvols is None:
+        return None
+    sv = (SubVolume * max(n, 1))()
+    for i, (off, (nz, ny, nx), (gz, gy, gx)) in enumerate(subvols):
+        sv[i] = SubVolume(int(off), int(nx), int(ny), int(nz), int(gx), int(gy), int(gz))
+    return sv
+
+
+def fill_bricks(coarse_prob, labels, factor, bricks, prob_out, subvols=None, ctx=None):
     """Upsampled coarse probabilities (seeds exact) into the listed bricks of prob_out."""
     ctx = ctx or default_context()
     arr = _bricks_array(bricks)
     _check(lib().rw_fill_bricks(ctx.handle, _ptr(coarse_prob), _dt_code(coarse_prob),
                                 _dims(coarse_prob.shape[1:]), int(coarse_prob.shape[0]), int(factor),
-                                _ptr(labels), _dims(labels.shape), arr, len(bricks), _ptr(prob_out),
+                                _ptr(labels), _dims(labels.shape), arr,
+                                _subvols_array(subvols, len(bricks)), len(bricks), _ptr(prob_out),
                                 _stream()), "rw_fill_bricks")
     return prob_out
 
 
 def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=None, tol=1e-6,
-                 precision="mixed", lo=None, hi=None, ctx=None, return_stats=False, **kw):
-    """Batched brick solves; returns (prob_out [K][grid] float32, iters [n][R])."""
+                 precision="mixed", lo=None, hi=None, ctx=None, return_stats=False, subvols=None,
+                 workspace=None, **kw):
+    """Batched brick solves; returns (prob_out [K][grid] float32, iters [n][R]).
+
+    subvols: None (bricks in `vol`), or per brick (offset, (nz, ny, nx),
+    (gz, gy, gx)) of its sub-volume in the flat pool `vol`/`labels`."""
     ctx = ctx or default_context()
     V = make_volume(vol, lo, hi)
     S = _seeds(labels, K)
@@ -424,13 +444,15 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
     n = len(bricks)
     R = K if o.solve_all_labels else K - 1
     nbytes = lib().rw_bricks_workspace_bytes(arr, n, K, o.precision, o.solve_all_labels)
-    ws = _alloc_ws(nbytes, vol.device)
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _alloc_ws(
+        nbytes, vol.device)
     iters = (ctypes.c_int32 * max(n * R, 1))()
+    sv = _subvols_array(subvols, n)
     st = Stats()
     status = lib().rw_solve_bricks(ctx.handle, ctypes.byref(V), ctypes.byref(S), _ptr(coarse_prob),
                                    _dt_code(coarse_prob), _dims(coarse_prob.shape[1:]), int(factor),
-                                   arr, n, ctypes.byref(o), _ptr(prob_out), iters, _ptr(ws), nbytes,
-                                   ctypes.byref(st), _stream())
+                                   arr, sv, n, ctypes.byref(o), _ptr(prob_out), iters, _ptr(ws),
+                                   nbytes, ctypes.byref(st), _stream())
     _check(status, "rw_solve_bricks")
     it = [[iters[i * R + r] for r in range(R)] for i in range(n)]
     if return_stats:
@@ -442,7 +464,8 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
 
 def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offset=(0, 0, 0),
                        tol=1e-6, coarse_precision="fp64", brick_precision="mixed", lo=None,
-                       hi=None, lo_thr=0.02, hi_thr=0.98, ctx=None, return_info=False):
+                       hi=None, lo_thr=0.02, hi_thr=0.98, ctx=None, return_info=False,
+                       level_dtype=torch.float64):
     """Coarse-to-fine random walker: LOD levels, whole coarse solve, brick
     classification, batched solve of the uncertain bricks, upsampled fill of
     the others.  Every step runs in the library; this only sequences calls."""
@@ -451,7 +474,7 @@ def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offse
     g, lab = vol, labels
     glo, ghi = V.norm_lo, V.norm_hi
     for _ in range(levels):
-        g, lab = downsample(g, lab, lo=glo, hi=ghi, out_dtype=torch.float64, ctx=ctx)
+        g, lab = downsample(g, lab, lo=glo, hi=ghi, out_dtype=level_dtype, ctx=ctx)
         glo, ghi = 0.0, 1.0
     coarse, _, cst = solve(g, lab, K, beta, tol=tol, precision=coarse_precision, lo=0.0, hi=1.0,
                            argmax=False, ctx=ctx, return_stats=True)
