@@ -1,20 +1,43 @@
-// Tile shapes of the stencil kernels: the tuned table and its overrides.
+// Tile shapes of the stencil kernels: the measured default, the table filled
+// by the autotuner, and overrides.
+#include <cmath>
 #include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "rw_internal.h"
 #include "rw_kernels.h"
 
 namespace rw {
 
-static int env_int(const char* name, int dflt) {
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, TileChoice> g_tuned;  // (precision, R, size class)
+thread_local bool g_forced = false;
+thread_local TileChoice g_force{4, 32, 0};
+
+int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     return v && *v ? std::atoi(v) : dflt;
 }
 
+int size_class(const Geom& G) {
+    return G.n > 0 ? int(std::floor(std::log2(double(G.n)))) : 0;
+}
+
+}  // namespace
+
 TileChoice tuned_tiles(const Geom& G, int precision, int R) {
-    (void)G;
-    (void)precision;
-    (void)R;
+    if (g_forced) return g_force;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(std::make_tuple(precision, R, size_class(G)));
+        if (it != g_tuned.end()) return it->second;
+    }
     // measured on MI355X (512^3, two labels): float32 passes prefer the
     // XCD-aware tile order, float64 passes the plain one
     TileChoice c{4, 32, precision == RW_PREC_MIXED ? 1 : 0};
@@ -27,3 +50,60 @@ TileChoice tuned_tiles(const Geom& G, int precision, int R) {
 }
 
 }  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                      const rw_options* opts, void* prob_scratch, void* ws, size_t ws_bytes,
+                      int32_t* best, void* stream) {
+    if (!ctx || !vol || !seeds || !opts || !prob_scratch) return invalid("NULL argument");
+    rw_status e = check_volume(vol);
+    if (e) return e;
+    const Geom G = make_geom(vol->dims);
+    const int K = seeds->num_labels;
+    const int R = std::max(1, std::min(4, opts->solve_all_labels ? K : K - 1));
+    static const int bys[] = {4, 8};
+    static const int zcs[] = {16, 32, 64};
+    static const int xcds[] = {0, 1};
+    rw_options o = *opts;
+    o.kernel_timing = 1;
+    o.use_graph = 0;
+    o.max_iter = std::max(2, o.check_interval) * 2;
+    o.x0 = nullptr;
+    double best_t = INFINITY;
+    TileChoice win = tuned_tiles(G, opts->precision, R);
+    for (int by : bys)
+        for (int zc : zcs)
+            for (int xcd : xcds) {
+                g_forced = true;
+                g_force = TileChoice{by, zc, xcd};
+                rw_stats st;
+                memset(&st, 0, sizeof(st));
+                // every candidate writes the scratch output
+                e = rw_solve(ctx, vol, seeds, &o, prob_scratch, nullptr, ws, ws_bytes, &st,
+                             stream);
+                g_forced = false;
+                if (e < 0) return e;
+                const int64_t l = st.pass_launches[0] + st.pass_launches[1];
+                if (l <= 0) continue;
+                const double t = (st.pass_ms[0] + st.pass_ms[1]) / double(l);
+                if (t < best_t) {
+                    best_t = t;
+                    win = TileChoice{by, zc, xcd};
+                }
+            }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple(opts->precision, R, size_class(G))] = win;
+    }
+    if (best) {
+        best[0] = win.by;
+        best[1] = win.zc;
+        best[2] = win.xcd;
+    }
+    return RW_OK;
+}
+
+}  // extern "C"

@@ -37,7 +37,7 @@ EXPORTS = [
     "rw_default_options", "rw_minmax", "rw_build_weights", "rw_operator_workspace_bytes",
     "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
-    "rw_backward_workspace_bytes", "rw_solve_backward",
+    "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune",
 ]
 
 
@@ -153,6 +153,8 @@ def lib():
     L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                                     ctypes.POINTER(Options), I32, P, P, P, ctypes.POINTER(D), P,
                                     SZ, ctypes.POINTER(Stats), P]
+    L.rw_autotune.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
+                              ctypes.POINTER(Options), P, P, SZ, ctypes.POINTER(I32), P]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is ctypes.c_int:
@@ -559,3 +561,22 @@ def random_walker(g, beta, labels, K, tol=1e-10, solve_all_labels=False):
     if not torch.is_tensor(beta):
         beta = torch.tensor(float(beta), dtype=torch.float64, device=g.device)
     return RandomWalkerFn.apply(g, beta, labels, K, tol, solve_all_labels)
+
+
+def autotune(vol, labels, K, beta, precision="mixed", lo=None, hi=None, ctx=None, **kw):
+    """Pick and record the fastest stencil tile shape for this volume; returns (by, zc, xcd)."""
+    import warnings
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, K)
+    o = options(beta, 1e-6, precision, **kw)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    prob = torch.empty((K,) + tuple(vol.shape), dtype=dt, device=vol.device)
+    nbytes = lib().rw_solve_workspace_bytes(_dims(vol.shape), K, o.precision, o.solve_all_labels)
+    ws = _alloc_ws(nbytes, vol.device)
+    best = (ctypes.c_int32 * 3)()
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        _check(lib().rw_autotune(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
+                                 _ptr(prob), _ptr(ws), nbytes, best, _stream()), "rw_autotune")
+    return tuple(best)

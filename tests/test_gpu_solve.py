@@ -278,3 +278,15 @@ def test_workspace_too_small(rw):
                            ctypes.byref(o), rw._ptr(prob), None, rw._ptr(ws), 16, None,
                            rw._stream())
     assert st == rw.RW_ERR_WORKSPACE
+
+
+def test_autotuner_records_a_tile_and_solves_agree(rw):
+    c = blob_case(shape=(48, 64, 96), n_blobs=5, K=3, seeds_per_label=30, sigma=0.08,
+                  rmin=4, rmax=12, seed=17)
+    vol, lab = _case_tensors(c)
+    ref, _ = _oracle_same(c)
+    by, zc, xcd = rw.autotune(vol, lab, 3, c.beta, precision="mixed")
+    assert by in (4, 8) and zc in (16, 32, 64) and xcd in (0, 1)
+    prob, _, st = rw.solve(vol, lab, 3, c.beta, precision="mixed", return_stats=True)
+    assert st["tile"][0] == by
+    assert_parity(host(prob), ref, what="after autotune")
