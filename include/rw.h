@@ -114,7 +114,8 @@ typedef struct {
     int32_t num_solved;                  /* R */
     int32_t refinements;                 /* mixed: float64 residual recomputations
                                             after the first */
-    int32_t tile_by, tile_zc;            /* stencil tile used (64 x by, zc planes) */
+    int32_t tile_by, tile_zc;            /* stencil tile used (64 vx x by columns,
+                                            zc planes; vx and xcd at the end) */
     double device_ms;                    /* whole call on the device (events) */
     double loop_ms;                      /* CG iteration loops only */
     /* kernel_timing = 1: summed durations of the CG passes over the iterations
@@ -130,6 +131,8 @@ typedef struct {
     int64_t rhs_voxel_iterations;
     int64_t active_bricks;               /* brick solves: bricks solved */
     int64_t unknowns;                    /* unseeded voxels solved for */
+    int32_t tile_vx;                     /* columns per lane (1, 2, 4) */
+    int32_t tile_xcd;                    /* 1: XCD-aware tile order */
 } rw_stats;
 
 /* Fine-level brick: origin and size in voxels of the fine grid (or of its
@@ -280,14 +283,15 @@ rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seed
                             const double* grad_x, double* grad_g_out, double* grad_beta_out,
                             void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
 
-/* Tile-shape autotuner of the stencil kernels (64 x by columns, zc planes,
- * XCD-aware tile order on/off): runs 2 * check_interval CG iterations of
- * rw_solve on this volume for each candidate (by in {4, 8}, zc in
- * {16, 32, 64}, order in {plain, XCD-aware}) with every pass timed by events,
+/* Tile-shape autotuner of the whole-volume stencil kernels (64 vx x 4
+ * columns, each lane owning vx columns 64 apart; zc planes; XCD-aware tile
+ * order on/off): runs 2 * check_interval CG iterations of rw_solve on this
+ * volume for each candidate (vx in {1, 2, 4}, 4 for mixed precision only; zc
+ * in {16, 32, 64}; order in {plain, XCD-aware}) with every pass timed by events,
  * and records the fastest for later solves of the same precision, number of
  * solved labels and size class (floor(log2 voxels)) in this process.
  * prob_scratch: output buffer as for rw_solve (overwritten); ws as for
- * rw_solve; best: host, 3 ints (by, zc, xcd) or NULL. */
+ * rw_solve; best: host, 3 ints (vx, zc, xcd) or NULL. */
 rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                       const rw_options* opts, void* prob_scratch, void* ws, size_t ws_bytes,
                       int32_t* best, void* stream);

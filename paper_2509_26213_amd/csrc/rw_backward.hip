@@ -65,7 +65,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_sum1(const double* __restrict__
     if (threadIdx.x == 0) out[0] = sums[0];
 }
 
-template <typename V, int BY>
+template <typename V, int VX>
 static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                                const rw_options* o, int label, const double* x_full,
                                const double* grad_x, double* grad_g, double* grad_beta,
@@ -78,13 +78,13 @@ static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint
     const TileChoice tc = choose_tiles(G, RW_PREC_FP64, 1);
     rw_options fo = *o;
     fo.precision = RW_PREC_FP64;
-    WholeSolve<V, double, 1, BY> S;
+    WholeSolve<V, double, 1, VX> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(vol->data);
     S.lab = lab;
     S.G = G;
     S.wc = make_wcoef(vol, o->beta, o->w_eps);
-    S.tm = make_tilemap(G, BY, tc.zc, tc.xcd);
+    S.tm = make_tilemap(G, WholeSolve<V, double, 1, VX>::BY, tc.zc, tc.xcd, VX);
     S.lab0 = 0;  // zero Dirichlet data: lam = 0 on seeds
     S.mixed = false;
     S.reliable = false;
@@ -135,10 +135,10 @@ static rw_status backward_v(rw_context* ctx, const rw_volume* vol, const uint8_t
                             const double* grad_x, double* grad_g, double* grad_beta, void* ws,
                             rw_stats* stats) {
     const TileChoice tc = choose_tiles(make_geom(vol->dims), RW_PREC_FP64, 1);
-    if (tc.by == 8)
-        return backward_impl<V, 8>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
+    if (tc.vx == 2)
+        return backward_impl<V, 2>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
                                    stats);
-    return backward_impl<V, 4>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
+    return backward_impl<V, 1>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
                                stats);
 }
 

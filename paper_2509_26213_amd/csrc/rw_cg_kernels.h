@@ -2,8 +2,9 @@
 //
 // A system is solved on a box of the grid: the whole volume, or one brick of
 // the fine level (whose face shell then carries Dirichlet data).  A box is cut
-// into tiles of 64 x BY columns by zc planes; a block of 64 x BY threads walks
-// a tile's planes in batches of U.  Per batch it issues every global load
+// into tiles of 64 VX x BY columns by zc planes; a block of 64 x BY threads
+// walks a tile's planes in batches of U, each lane owning VX columns 64 apart
+// (so every load instruction of a wave reads 64 consecutive values).  Per batch it issues every global load
 // (unconditionally, from clamped addresses, values outside the volume or box
 // replaced by selects), then publishes the batch's planes of intensity and CG
 // operand, with their one-voxel x/y halo, to LDS; in-plane neighbours come
@@ -23,6 +24,18 @@ namespace rw {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Element i of a row/plane whose base is wave-uniform, addressed by a 32-bit
+// byte offset (the loads then take the base in scalar registers and only the
+// 32-bit offset per lane).
+template <typename P>
+__device__ __forceinline__ P ld(const P* __restrict__ base, uint32_t i) {
+    return *reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + i * uint32_t(sizeof(P)));
+}
+template <typename P>
+__device__ __forceinline__ void stu(P* __restrict__ base, uint32_t i, P v) {
+    *reinterpret_cast<P*>(reinterpret_cast<char*>(base) + i * uint32_t(sizeof(P))) = v;
+}
+
 struct BoxTile {
     Geom G;                  // the volume the box lives in
     int64_t voff;            // offset of that volume in the intensity / label arrays
@@ -30,6 +43,7 @@ struct BoxTile {
     int ox, oy, oz;          // box origin in the volume
     int sx, sy, sz;          // box size
     int X0, Y0, z0, z1;      // tile origin (box-local) and plane range [z0, z1)
+    int tw;                  // tile width in columns (64 vx)
     int64_t vbase, vstride;  // vector offset of the box's first label, label stride
     int sidx;                // box index: RhsState rows sidx*R .. sidx*R+R-1
     int pidx;                // partial slot of the tile
@@ -51,7 +65,8 @@ struct WholeTiles {
         b.sx = G.nx;
         b.sy = G.ny;
         b.sz = G.nz;
-        b.X0 = tx * 64;
+        b.tw = 64 * tm.vx;
+        b.X0 = tx * b.tw;
         b.Y0 = ty * tm.by;
         b.z0 = tz * tm.zc;
         b.z1 = min(b.z0 + tm.zc, G.nz);
@@ -105,6 +120,7 @@ struct BrickTiles {
         b.sx = B.sx;
         b.sy = B.sy;
         b.sz = B.sz;
+        b.tw = 64;
         b.X0 = tx * 64;
         b.Y0 = ty * by;
         b.z0 = tz * zc;
@@ -204,8 +220,10 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
         double acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-        const int lxb = bt.X0 + threadIdx.x, lyb = bt.Y0 + threadIdx.y;
-        if (lxb < bt.sx && lyb < bt.sy) {
+        const int lyb = bt.Y0 + threadIdx.y;
+        for (int sub = 0; sub < bt.tw; sub += 64) {
+            const int lxb = bt.X0 + sub + threadIdx.x;
+            if (lxb >= bt.sx || lyb >= bt.sy) continue;
             const int gx = bt.ox + lxb, gy = bt.oy + lyb;
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
                 const int gz = bt.oz + lz;
@@ -312,57 +330,71 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
 
 // ---------------------------------------------------------------- CG passes
 
-template <int BY, int U>
+template <int BY, int U, int VX>
 struct TileLanes {
     static constexpr int NYH = (2 * U + BY - 1) / BY;  // y-halo rows per wave per batch
+    static constexpr int TW = 64 * VX;                 // tile width
     int lx, ly;
-    int lxb, lyb;         // own position, box-local
-    int gx, gy;           // own position, global
-    bool in_box, in_vol;  // own column inside the box / the volume
-    int64_t colv, colb;   // clamped own column offset in the volume / in the box
+    int gy;                           // own row, global
+    int gx[VX];                       // own columns, global
+    bool in_box[VX], in_vol[VX];      // own column v inside the box / the volume
+    uint32_t colv[VX], colb[VX];      // clamped in-plane offsets in the volume / the box
     bool hx_use, hx_vol, hx_box;
     int hx_k, hx_col_lds;
-    int64_t hx_colv, hx_colb;
-    bool hy_use[NYH], hy_vol[NYH], hy_box[NYH];
+    uint32_t hx_colv, hx_colb;
+    bool hy_use[NYH];
+    bool hy_vol[NYH][VX], hy_box[NYH][VX];
     int hy_k[NYH], hy_row_lds[NYH];
-    int64_t hy_colv[NYH], hy_colb[NYH];
+    uint32_t hy_colv[NYH][VX], hy_colb[NYH][VX];
 
     __device__ __forceinline__ void init(const Geom& G, const BoxTile& b) {
         lx = threadIdx.x;
         ly = threadIdx.y;
-        lxb = b.X0 + lx;
-        lyb = b.Y0 + ly;
-        gx = b.ox + lxb;
+        const int lyb = b.Y0 + ly;
         gy = b.oy + lyb;
-        in_box = lxb < b.sx && lyb < b.sy;
-        in_vol = gx < G.nx && gy < G.ny;
-        const int cgx = min(gx, G.nx - 1), cgy = min(gy, G.ny - 1);
-        const int cbx = min(lxb, b.sx - 1), cby = min(lyb, b.sy - 1);
-        colv = (int64_t)cgy * G.nx + cgx;
-        colb = (int64_t)cby * b.sx + cbx;
+        const int cgy = min(gy, G.ny - 1), cby = min(lyb, b.sy - 1);
+        int cgx[VX], cbx[VX], lxb[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            lxb[v] = b.X0 + 64 * v + lx;
+            gx[v] = b.ox + lxb[v];
+            in_box[v] = lxb[v] < b.sx && lyb < b.sy;
+            in_vol[v] = gx[v] < G.nx && gy < G.ny;
+            cgx[v] = min(gx[v], G.nx - 1);
+            cbx[v] = min(lxb[v], b.sx - 1);
+            colv[v] = uint32_t(cgy) * uint32_t(G.nx) + uint32_t(cgx[v]);
+            colb[v] = uint32_t(cby) * uint32_t(b.sx) + uint32_t(cbx[v]);
+        }
+        // x halo: lanes 0 .. 2U-1, one value each (side = lane parity, plane = lane / 2)
         const int side = lx & 1;
         hx_k = min(lx >> 1, U - 1);
         hx_use = lx < 2 * U;
-        const int hxb = side ? b.X0 + 64 : b.X0 - 1;
+        const int hxb = side ? b.X0 + TW : b.X0 - 1;
         const int hgx = b.ox + hxb;
         hx_vol = hx_use && hgx >= 0 && hgx < G.nx && gy < G.ny;
         hx_box = hx_use && hxb >= 0 && hxb < b.sx && lyb < b.sy;
-        hx_colv = (int64_t)cgy * G.nx + clampi(hgx, 0, G.nx - 1);
-        hx_colb = (int64_t)cby * b.sx + clampi(hxb, 0, b.sx - 1);
-        hx_col_lds = side ? 65 : 0;
+        hx_colv = uint32_t(cgy) * uint32_t(G.nx) + uint32_t(clampi(hgx, 0, G.nx - 1));
+        hx_colb = uint32_t(cby) * uint32_t(b.sx) + uint32_t(clampi(hxb, 0, b.sx - 1));
+        hx_col_lds = side ? TW + 1 : 0;
+        // y halo: 2U rows (side, plane) spread over the waves, TW values each
 #pragma unroll
         for (int j = 0; j < NYH; ++j) {
             const int i = ly + j * BY;
             hy_use[j] = i < 2 * U;
-            const int s = i & 1;
+            const int sy = i & 1;
             hy_k[j] = min(i >> 1, U - 1);
-            const int yb = s ? b.Y0 + BY : b.Y0 - 1;
+            const int yb = sy ? b.Y0 + BY : b.Y0 - 1;
             const int gyh = b.oy + yb;
-            hy_vol[j] = hy_use[j] && gyh >= 0 && gyh < G.ny && gx < G.nx;
-            hy_box[j] = hy_use[j] && yb >= 0 && yb < b.sy && lxb < b.sx;
-            hy_colv[j] = (int64_t)clampi(gyh, 0, G.ny - 1) * G.nx + cgx;
-            hy_colb[j] = (int64_t)clampi(yb, 0, b.sy - 1) * b.sx + cbx;
-            hy_row_lds[j] = s ? BY + 1 : 0;
+            const uint32_t rv = uint32_t(clampi(gyh, 0, G.ny - 1)) * uint32_t(G.nx);
+            const uint32_t rb = uint32_t(clampi(yb, 0, b.sy - 1)) * uint32_t(b.sx);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                hy_vol[j][v] = hy_use[j] && gyh >= 0 && gyh < G.ny && gx[v] < G.nx;
+                hy_box[j][v] = hy_use[j] && yb >= 0 && yb < b.sy && lxb[v] < b.sx;
+                hy_colv[j][v] = rv + uint32_t(cgx[v]);
+                hy_colb[j][v] = rb + uint32_t(cbx[v]);
+            }
+            hy_row_lds[j] = sy ? BY + 1 : 0;
         }
     }
 };
@@ -400,18 +432,48 @@ __device__ __forceinline__ int box_labels(const RhsState* __restrict__ st, int s
     return first;
 }
 
+// The five edge weights of a voxel in plane k, column v of the LDS tile
+// (-x, +x, -y, +y from LDS, +z from the registers), zero across the volume
+// border; d adds the -z weight carried from the previous plane.
+template <typename T, int BY, int U, int VX>
+struct Stencil {
+    T wxm, wxp, wym, wyp, wzp, d;
+    __device__ __forceinline__ void eval(const T (&sg)[U][BY + 2][64 * VX + 2], int k, int v,
+                                         const TileLanes<BY, U, VX>& L, const Geom& G, int gz,
+                                         T gc, T gzn, T wzm, const WCoef& wc) {
+        const int c = 64 * v + L.lx;
+        wxm = L.gx[v] > 0 ? Weight<T>::of(gc - sg[k][L.ly + 1][c], wc) : T(0);
+        wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][L.ly + 1][c + 2], wc) : T(0);
+        wym = L.gy > 0 ? Weight<T>::of(gc - sg[k][L.ly][c + 1], wc) : T(0);
+        wyp = L.gy + 1 < G.ny ? Weight<T>::of(gc - sg[k][L.ly + 2][c + 1], wc) : T(0);
+        wzp = gz + 1 < G.nz ? Weight<T>::of(gc - gzn, wc) : T(0);
+        d = wxm + wxp + wym + wyp + wzm + wzp;
+    }
+    // q = d p - sum_j w_j p_j
+    __device__ __forceinline__ T apply(const T (&sp)[U][BY + 2][64 * VX + 2], int k, int v,
+                                       const TileLanes<BY, U, VX>& L, T wzm, T pc, T pzm,
+                                       T pzp) const {
+        const int c = 64 * v + L.lx;
+        return d * pc - (wxm * sp[k][L.ly + 1][c] + wxp * sp[k][L.ly + 1][c + 2] +
+                         wym * sp[k][L.ly][c + 1] + wyp * sp[k][L.ly + 2][c + 1] + wzm * pzm +
+                         wzp * pzp);
+    }
+};
+
 // Pass 1: p_new = z + beta p_old (formed on the fly for the voxel and its
 // neighbours; zero on seeds and outside the box), q = A p_new, partial
 // p_new.q per label.  Label r reads p_old from buffer st.pcur of pb0/pb1 and
 // writes p_new to the other one.  qout (optional) receives q.
-template <typename V, typename T, int R, int BY, int U, typename TS>
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
     const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
     const RhsState* __restrict__ st, double* __restrict__ part) {
-    constexpr int NYH = TileLanes<BY, U>::NYH;
-    __shared__ T sg[U][BY + 2][66];
-    __shared__ T sp[R][U][BY + 2][66];
+    using Lanes = TileLanes<BY, U, VX>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int TW = Lanes::TW;
+    __shared__ T sg[U][BY + 2][TW + 2];
+    __shared__ T sp[R][U][BY + 2][TW + 2];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -433,60 +495,74 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
             po[r] = (s.pcur ? pb1 : pb0) + bt.vbase + src[r] * bt.vstride;
             pw[r] = (st[bt.sidx * R + r].pcur ? pb0 : pb1) + bt.vbase + r * bt.vstride;
         }
-        TileLanes<BY, U> L;
+        Lanes L;
         L.init(G, bt);
+        const int64_t bplane = (int64_t)bt.sx * bt.sy;
 
-        T Gv[U + 2], Pv[U + 2][R];  // own column: planes z-1, z, z+1 .. z+U
+        T Gv[U + 2][VX], Pv[U + 2][R][VX];  // own columns: planes z-1, z, z+1 .. z+U
         {
             const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
-            Gv[0] = (T)vol[om.v + L.colv];
-            Gv[1] = (T)vol[oc.v + L.colv];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T a = zr[r][om.b + L.colb] + bet[r] * po[r][om.b + L.colb];
-                Pv[0][r] = om.inb ? a : T(0);
-                Pv[1][r] = zr[r][oc.b + L.colb] + bet[r] * po[r][oc.b + L.colb];
+            for (int v = 0; v < VX; ++v) {
+                Gv[0][v] = (T)ld(vol + om.v, L.colv[v]);
+                Gv[1][v] = (T)ld(vol + oc.v, L.colv[v]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T a = ld(zr[r] + om.b, L.colb[v]) + bet[r] * ld(po[r] + om.b, L.colb[v]);
+                    Pv[0][r][v] = om.inb ? a : T(0);
+                    Pv[1][r][v] = ld(zr[r] + oc.b, L.colb[v]) + bet[r] * ld(po[r] + oc.b, L.colb[v]);
+                }
             }
         }
-        T wzm = (L.in_box && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1] - Gv[0], wc) : T(0);
+        T wzm[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v)
+            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                                                         : T(0);
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
 
         for (int zb = bt.z0; zb < bt.z1; zb += U) {
             // (1) every read of the batch
-            T zN[U][R], oN[U][R];
+            T zN[U][R][VX], oN[U][R][VX];
             bool nin[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const PlaneOff o = plane_off(G, bt, zb + 1 + k);
                 nin[k] = o.inb;
-                Gv[k + 2] = (T)vol[o.v + L.colv];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    zN[k][r] = zr[r][o.b + L.colb];
-                    oN[k][r] = po[r][o.b + L.colb];
+                for (int v = 0; v < VX; ++v) {
+                    Gv[k + 2][v] = (T)ld(vol + o.v, L.colv[v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        zN[k][r][v] = ld(zr[r] + o.b, L.colb[v]);
+                        oN[k][r][v] = ld(po[r] + o.b, L.colb[v]);
+                    }
                 }
             }
             T hxg, hxz[R], hxo[R];
             {
                 const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)vol[o.v + L.hx_colv];
+                hxg = (T)ld(vol + o.v, L.hx_colv);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    hxz[r] = zr[r][o.b + L.hx_colb];
-                    hxo[r] = po[r][o.b + L.hx_colb];
+                    hxz[r] = ld(zr[r] + o.b, L.hx_colb);
+                    hxo[r] = ld(po[r] + o.b, L.hx_colb);
                 }
             }
-            T hyg[NYH], hyz[NYH][R], hyo[NYH][R];
+            T hyg[NYH][VX], hyz[NYH][R][VX], hyo[NYH][R][VX];
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
-                hyg[j] = (T)vol[o.v + L.hy_colv[j]];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    hyz[j][r] = zr[r][o.b + L.hy_colb[j]];
-                    hyo[j][r] = po[r][o.b + L.hy_colb[j]];
+                for (int v = 0; v < VX; ++v) {
+                    hyg[j][v] = (T)ld(vol + o.v, L.hy_colv[j][v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        hyz[j][r][v] = ld(zr[r] + o.b, L.hy_colb[j][v]);
+                        hyo[j][r][v] = ld(po[r] + o.b, L.hy_colb[j][v]);
+                    }
                 }
             }
             // (2) the previous batch (or tile) is done with the LDS planes
@@ -494,15 +570,20 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
             // (3) publish planes zb..zb+U-1
 #pragma unroll
             for (int k = 0; k < U; ++k) {
-                if (k > 0) {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    if (k > 0) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            Pv[k + 1][r][v] =
+                                nin[k - 1] ? zN[k - 1][r][v] + bet[r] * oN[k - 1][r][v] : T(0);
+                    }
+                    const int c = 64 * v + L.lx + 1;
+                    sg[k][L.ly + 1][c] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        Pv[k + 1][r] = nin[k - 1] ? zN[k - 1][r] + bet[r] * oN[k - 1][r] : T(0);
+                        sp[r][k][L.ly + 1][c] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
                 }
-                sg[k][L.ly + 1][L.lx + 1] = L.in_vol ? Gv[k + 1] : T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    sp[r][k][L.ly + 1][L.lx + 1] = L.in_box ? Pv[k + 1][r] : T(0);
             }
             if (L.hx_use) {
                 sg[L.hx_k][L.ly + 1][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
@@ -514,52 +595,61 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 if (L.hy_use[j]) {
-                    sg[L.hy_k[j]][L.hy_row_lds[j]][L.lx + 1] = L.hy_vol[j] ? hyg[j] : T(0);
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        sp[r][L.hy_k[j]][L.hy_row_lds[j]][L.lx + 1] =
-                            L.hy_box[j] ? hyz[j][r] + bet[r] * hyo[j][r] : T(0);
+                    for (int v = 0; v < VX; ++v) {
+                        const int c = 64 * v + L.lx + 1;
+                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][v] ? hyg[j][v] : T(0);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
+                                L.hy_box[j][v] ? hyz[j][r][v] + bet[r] * hyo[j][r][v] : T(0);
+                    }
                 }
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                Pv[U + 1][r] = nin[U - 1] ? zN[U - 1][r] + bet[r] * oN[U - 1][r] : T(0);
+            for (int v = 0; v < VX; ++v)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    Pv[U + 1][r][v] =
+                        nin[U - 1] ? zN[U - 1][r][v] + bet[r] * oN[U - 1][r][v] : T(0);
             __syncthreads();
             // (4) stencil on planes zb..zb+U-1
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int lz = zb + k;
                 const int gz = bt.oz + lz;
-                const T gc = Gv[k + 1];
-                const T wxm = L.gx > 0 ? Weight<T>::of(gc - sg[k][L.ly + 1][L.lx], wc) : T(0);
-                const T wxp = L.gx + 1 < G.nx ? Weight<T>::of(gc - sg[k][L.ly + 1][L.lx + 2], wc) : T(0);
-                const T wym = L.gy > 0 ? Weight<T>::of(gc - sg[k][L.ly][L.lx + 1], wc) : T(0);
-                const T wyp = L.gy + 1 < G.ny ? Weight<T>::of(gc - sg[k][L.ly + 2][L.lx + 1], wc) : T(0);
-                const T wzp = gz + 1 < G.nz ? Weight<T>::of(gc - Gv[k + 2], wc) : T(0);
-                const T d = wxm + wxp + wym + wyp + wzm + wzp;
-                const bool valid = L.in_box && lz < bt.z1;
-                const int64_t ob = (int64_t)lz * bt.sx * bt.sy + L.colb;
+                const bool zin = lz < bt.z1;
+                T* __restrict__ prow[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T pc = Pv[k + 1][r];
-                    const T q = d * pc - (wxm * sp[r][k][L.ly + 1][L.lx] + wxp * sp[r][k][L.ly + 1][L.lx + 2] +
-                                          wym * sp[r][k][L.ly][L.lx + 1] + wyp * sp[r][k][L.ly + 2][L.lx + 1] +
-                                          wzm * Pv[k][r] + wzp * Pv[k + 2][r]);
-                    if (valid && act[r]) {
-                        pw[r][ob] = pc;
-                        if (qout) qout[bt.vbase + r * bt.vstride + ob] = q;
-                        acc[r] += (double)pc * (double)q;
+                for (int r = 0; r < R; ++r) prow[r] = pw[r] + (int64_t)lz * bplane;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    Stencil<T, BY, U, VX> S;
+                    S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                    const bool valid = L.in_box[v] && zin;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T pc = Pv[k + 1][r][v];
+                        const T q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                        if (valid && act[r]) {
+                            stu(prow[r], L.colb[v], pc);
+                            if (qout) qout[bt.vbase + r * bt.vstride + (int64_t)lz * bplane + L.colb[v]] = q;
+                            acc[r] += (double)pc * (double)q;
+                        }
                     }
+                    wzm[v] = S.wzp;
                 }
-                wzm = wzp;
             }
             // (5) carry planes zb+U-1 and zb+U
-            Gv[0] = Gv[U];
-            Gv[1] = Gv[U + 1];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                Pv[0][r] = Pv[U][r];
-                Pv[1][r] = Pv[U + 1][r];
+            for (int v = 0; v < VX; ++v) {
+                Gv[0][v] = Gv[U][v];
+                Gv[1][v] = Gv[U + 1][v];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    Pv[0][r][v] = Pv[U][r][v];
+                    Pv[1][r][v] = Pv[U + 1][r][v];
+                }
             }
         }
         block_sum_store<R, BY>(acc, part + bt.pidx, ts.ntiles);
@@ -569,14 +659,16 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 // Pass 2: q = A p (p = buffer st.pcur, just written by pass 1); on unknowns
 // x += alpha p, r = d z - alpha q, z = r / d; partials r.z and r.r per label
 // ([2R][ntiles]).
-template <typename V, typename T, int R, int BY, int U, typename TS>
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
     const T* __restrict__ pb1, const RhsState* __restrict__ st, double* __restrict__ part) {
-    constexpr int NYH = TileLanes<BY, U>::NYH;
-    __shared__ T sg[U][BY + 2][66];
-    __shared__ T sp[R][U][BY + 2][66];
+    using Lanes = TileLanes<BY, U, VX>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int TW = Lanes::TW;
+    __shared__ T sg[U][BY + 2][TW + 2];
+    __shared__ T sp[R][U][BY + 2][TW + 2];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -589,8 +681,8 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
         const uint8_t* __restrict__ lab = labp + bt.voff;
         T alp[R];
         const T* pr[R];
-        const T* xr[R];
-        const T* zr[R];
+        T* xr[R];
+        T* zr[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             alp[r] = (T)st[bt.sidx * R + r].alpha;
@@ -599,69 +691,85 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
             xr[r] = xv + vb;
             zr[r] = zv + vb;
         }
-        TileLanes<BY, U> L;
+        Lanes L;
         L.init(G, bt);
 
-        T Gv[U + 2], Pv[U + 2][R];
+        T Gv[U + 2][VX], Pv[U + 2][R][VX];
         {
             const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
-            Gv[0] = (T)vol[om.v + L.colv];
-            Gv[1] = (T)vol[oc.v + L.colv];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T a = pr[r][om.b + L.colb];
-                Pv[0][r] = om.inb ? a : T(0);
-                Pv[1][r] = pr[r][oc.b + L.colb];
+            for (int v = 0; v < VX; ++v) {
+                Gv[0][v] = (T)ld(vol + om.v, L.colv[v]);
+                Gv[1][v] = (T)ld(vol + oc.v, L.colv[v]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T a = ld(pr[r] + om.b, L.colb[v]);
+                    Pv[0][r][v] = om.inb ? a : T(0);
+                    Pv[1][r][v] = ld(pr[r] + oc.b, L.colb[v]);
+                }
             }
         }
-        T wzm = (L.in_box && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1] - Gv[0], wc) : T(0);
+        T wzm[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v)
+            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                                                         : T(0);
         double acc[2 * R];
 #pragma unroll
         for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
 
         for (int zb = bt.z0; zb < bt.z1; zb += U) {
-            T Xv[U][R], Zv[U][R];
-            uint8_t Lv[U];
+            T Xv[U][R][VX], Zv[U][R][VX];
+            uint8_t Lv[U][VX];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const PlaneOff o = plane_off(G, bt, zb + 1 + k);
-                Gv[k + 2] = (T)vol[o.v + L.colv];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T a = pr[r][o.b + L.colb];
-                    Pv[k + 2][r] = o.inb ? a : T(0);
-                }
                 const PlaneOff oc = plane_off(G, bt, zb + k);
-                Lv[k] = lab[oc.v + L.colv];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    Xv[k][r] = xr[r][oc.b + L.colb];
-                    Zv[k][r] = zr[r][oc.b + L.colb];
+                for (int v = 0; v < VX; ++v) {
+                    Gv[k + 2][v] = (T)ld(vol + o.v, L.colv[v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T a = ld(pr[r] + o.b, L.colb[v]);
+                        Pv[k + 2][r][v] = o.inb ? a : T(0);
+                    }
+                    Lv[k][v] = ld(lab + oc.v, L.colv[v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        Xv[k][r][v] = ld(xr[r] + oc.b, L.colb[v]);
+                        Zv[k][r][v] = ld(zr[r] + oc.b, L.colb[v]);
+                    }
                 }
             }
             T hxg, hxp[R];
             {
                 const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)vol[o.v + L.hx_colv];
+                hxg = (T)ld(vol + o.v, L.hx_colv);
 #pragma unroll
-                for (int r = 0; r < R; ++r) hxp[r] = pr[r][o.b + L.hx_colb];
+                for (int r = 0; r < R; ++r) hxp[r] = ld(pr[r] + o.b, L.hx_colb);
             }
-            T hyg[NYH], hyp[NYH][R];
+            T hyg[NYH][VX], hyp[NYH][R][VX];
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
-                hyg[j] = (T)vol[o.v + L.hy_colv[j]];
 #pragma unroll
-                for (int r = 0; r < R; ++r) hyp[j][r] = pr[r][o.b + L.hy_colb[j]];
+                for (int v = 0; v < VX; ++v) {
+                    hyg[j][v] = (T)ld(vol + o.v, L.hy_colv[j][v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) hyp[j][r][v] = ld(pr[r] + o.b, L.hy_colb[j][v]);
+                }
             }
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < U; ++k) {
-                sg[k][L.ly + 1][L.lx + 1] = L.in_vol ? Gv[k + 1] : T(0);
+            for (int k = 0; k < U; ++k)
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    sp[r][k][L.ly + 1][L.lx + 1] = L.in_box ? Pv[k + 1][r] : T(0);
-            }
+                for (int v = 0; v < VX; ++v) {
+                    const int c = 64 * v + L.lx + 1;
+                    sg[k][L.ly + 1][c] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        sp[r][k][L.ly + 1][c] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
+                }
             if (L.hx_use) {
                 sg[L.hx_k][L.ly + 1][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
 #pragma unroll
@@ -671,10 +779,15 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 if (L.hy_use[j]) {
-                    sg[L.hy_k[j]][L.hy_row_lds[j]][L.lx + 1] = L.hy_vol[j] ? hyg[j] : T(0);
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        sp[r][L.hy_k[j]][L.hy_row_lds[j]][L.lx + 1] = L.hy_box[j] ? hyp[j][r] : T(0);
+                    for (int v = 0; v < VX; ++v) {
+                        const int c = 64 * v + L.lx + 1;
+                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][v] ? hyg[j][v] : T(0);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
+                                L.hy_box[j][v] ? hyp[j][r][v] : T(0);
+                    }
                 }
             }
             __syncthreads();
@@ -682,41 +795,42 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
             for (int k = 0; k < U; ++k) {
                 const int lz = zb + k;
                 const int gz = bt.oz + lz;
-                const T gc = Gv[k + 1];
-                const T wxm = L.gx > 0 ? Weight<T>::of(gc - sg[k][L.ly + 1][L.lx], wc) : T(0);
-                const T wxp = L.gx + 1 < G.nx ? Weight<T>::of(gc - sg[k][L.ly + 1][L.lx + 2], wc) : T(0);
-                const T wym = L.gy > 0 ? Weight<T>::of(gc - sg[k][L.ly][L.lx + 1], wc) : T(0);
-                const T wyp = L.gy + 1 < G.ny ? Weight<T>::of(gc - sg[k][L.ly + 2][L.lx + 1], wc) : T(0);
-                const T wzp = gz + 1 < G.nz ? Weight<T>::of(gc - Gv[k + 2], wc) : T(0);
-                const T d = wxm + wxp + wym + wyp + wzm + wzp;
-                const T dinv = T(1) / d;
-                const bool valid = L.in_box && lz < bt.z1 && Lv[k] == 0;
-                const int64_t ob = (int64_t)lz * bt.sx * bt.sy + L.colb;
+                const bool zin = lz < bt.z1;
+                const int64_t ob = (int64_t)lz * bt.sx * bt.sy;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    Stencil<T, BY, U, VX> S;
+                    S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                    const T dinv = T(1) / S.d;
+                    const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T pc = Pv[k + 1][r][v];
+                        const T q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                        const T xn = Xv[k][r][v] + alp[r] * pc;
+                        const T rres = S.d * Zv[k][r][v] - alp[r] * q;
+                        const T zn = dinv * rres;
+                        if (valid && act[r]) {
+                            T* __restrict__ xo = xv + bt.vbase + r * bt.vstride + ob;
+                            T* __restrict__ zo = zv + bt.vbase + r * bt.vstride + ob;
+                            stu(xo, L.colb[v], xn);
+                            stu(zo, L.colb[v], zn);
+                            acc[2 * r] += (double)rres * (double)zn;
+                            acc[2 * r + 1] += (double)rres * (double)rres;
+                        }
+                    }
+                    wzm[v] = S.wzp;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Gv[0][v] = Gv[U][v];
+                Gv[1][v] = Gv[U + 1][v];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const T pc = Pv[k + 1][r];
-                    const T q = d * pc - (wxm * sp[r][k][L.ly + 1][L.lx] + wxp * sp[r][k][L.ly + 1][L.lx + 2] +
-                                          wym * sp[r][k][L.ly][L.lx + 1] + wyp * sp[r][k][L.ly + 2][L.lx + 1] +
-                                          wzm * Pv[k][r] + wzp * Pv[k + 2][r]);
-                    const T xn = Xv[k][r] + alp[r] * pc;
-                    const T rres = d * Zv[k][r] - alp[r] * q;
-                    const T zn = dinv * rres;
-                    if (valid && act[r]) {
-                        const int64_t o = bt.vbase + r * bt.vstride + ob;
-                        xv[o] = xn;
-                        zv[o] = zn;
-                        acc[2 * r] += (double)rres * (double)zn;
-                        acc[2 * r + 1] += (double)rres * (double)rres;
-                    }
+                    Pv[0][r][v] = Pv[U][r][v];
+                    Pv[1][r][v] = Pv[U + 1][r][v];
                 }
-                wzm = wzp;
-            }
-            Gv[0] = Gv[U];
-            Gv[1] = Gv[U + 1];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                Pv[0][r] = Pv[U][r];
-                Pv[1][r] = Pv[U + 1][r];
             }
         }
         block_sum_store<2 * R, BY>(acc, part + bt.pidx, ts.ntiles);

@@ -629,7 +629,7 @@ static TileChoice brick_tiles(int precision) {
 
 template <typename V, typename T, int R, int BY>
 struct BrickSolve {
-    static constexpr int ZU = PlaneBatch<T>::value;
+    static constexpr int ZU = PlaneBatch<T, 1>::value;
     rw_context* ctx;
     const V* vol;
     const uint8_t* lab;
@@ -706,13 +706,13 @@ struct BrickSolve {
         hipStream_t s = ctx->s;
         const BrickTiles ta = act();
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
-        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, BrickTiles>), dim3(grid), dim3(64, BY), 0,
+        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0,
                            s, vol, wc, ta, (const T*)B.z, (T*)B.p0, (T*)B.p1, (T*)nullptr, B.st,
                            B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_bfin1<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, BrickTiles>), dim3(grid), dim3(64, BY), 0,
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0,
                            s, vol, lab, wc, ta, mixed ? (T*)B.xi : (T*)B.x64, (T*)B.z,
                            (const T*)B.p0, (const T*)B.p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));

@@ -20,8 +20,12 @@ rw_status ensure_dev_small(rw_context* ctx, size_t bytes);
 
 // Tile shape of the stencil kernels (64 x by columns, zc planes, XCD-aware
 // tile order on/off), from the tuning table or the environment.
+// Tile shape of the stencil kernels: 64 vx columns (each lane owns vx of
+// them, 64 apart) by `by` rows by zc planes, XCD-aware tile order or not.
+// Whole-volume solves use by = 4 and vx in {1, 2, 4}; brick solves vx = 1 and
+// by in {4, 8}.
 struct TileChoice {
-    int by, zc, xcd;
+    int by, zc, xcd, vx;
 };
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
 
@@ -98,7 +102,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 // range of tiles and the neighbour rows a tile re-reads were fetched into
 // the same XCD's L2 by the tile before it.
 struct TileMap {
-    int gx, gy, gz, zc, tiles, per, xcd, by;
+    int gx, gy, gz, zc, tiles, per, xcd, by, vx;
     __device__ __forceinline__ int tile(int b) const {
         if (!xcd) return b < tiles ? b : -1;
         const int t = (b & 7) * per + (b >> 3);
@@ -107,11 +111,12 @@ struct TileMap {
     __host__ __device__ int blocks() const { return xcd ? 8 * per : tiles; }
 };
 
-inline TileMap make_tilemap(const Geom& G, int by, int zc, int xcd) {
+inline TileMap make_tilemap(const Geom& G, int by, int zc, int xcd, int vx = 1) {
     TileMap m;
     m.by = by;
+    m.vx = vx;
     m.zc = zc;
-    m.gx = (G.nx + 63) / 64;
+    m.gx = (G.nx + 64 * vx - 1) / (64 * vx);
     m.gy = (G.ny + by - 1) / by;
     m.gz = (G.nz + zc - 1) / zc;
     m.tiles = m.gx * m.gy * m.gz;

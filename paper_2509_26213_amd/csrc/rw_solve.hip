@@ -36,10 +36,15 @@ static rw_status run_group(rw_context* ctx, const rw_volume* vol, const uint8_t*
                            const rw_options* o, int lab0, const double* x0, const GroupBuffers& B,
                            void* prob_out, rw_stats* stats, int r_base, int* worst) {
     const TileChoice tc = choose_tiles(make_geom(vol->dims), o->precision, R);
-    if (tc.by == 8)
-        return run_group_by<V, T, R, 8>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
+    if constexpr (std::is_same<T, float>::value) {
+        if (tc.vx == 4)
+            return run_group_vx<V, T, R, 4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
+                                            r_base, worst);
+    }
+    if (tc.vx == 2)
+        return run_group_vx<V, T, R, 2>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
                                         r_base, worst);
-    return run_group_by<V, T, R, 4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats, r_base,
+    return run_group_vx<V, T, R, 1>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats, r_base,
                                     worst);
 }
 
@@ -124,11 +129,12 @@ rw_status check_labels(rw_context* ctx, const uint8_t* lab, int64_t n, int K, in
     return RW_OK;
 }
 
-template <typename V, typename T, int BY>
-static rw_status apply_op_by(rw_context* ctx, const rw_volume* vol, const WCoef& wc,
+template <typename V, typename T, int VX>
+static rw_status apply_op_vx(rw_context* ctx, const rw_volume* vol, const WCoef& wc,
                              const TileChoice& tc, const void* p, void* q, void* ws) {
+    constexpr int BY = 4;
     const Geom G = make_geom(vol->dims);
-    const TileMap tm = make_tilemap(G, BY, tc.zc, tc.xcd);
+    const TileMap tm = make_tilemap(G, BY, tc.zc, tc.xcd, VX);
     Carver cv(ws);
     T* pnew = cv.take<T>(size_t(G.n));
     double* part = cv.take<double>(size_t(max_tiles(G)));
@@ -144,7 +150,7 @@ static rw_status apply_op_by(rw_context* ctx, const rw_volume* vol, const WCoef&
     ts.tm = tm;
     ts.G = G;
     ts.ntiles = tm.tiles;
-    hipLaunchKernelGGL((k_cg_pass1<V, T, 1, BY, PlaneBatch<T>::value, WholeTiles>),
+    hipLaunchKernelGGL((k_cg_pass1<V, T, 1, BY, PlaneBatch<T, VX>::value, VX, WholeTiles>),
                        dim3(unsigned(tm.blocks())), dim3(64, BY), 0, ctx->s, (const V*)vol->data,
                        wc, ts, (const T*)p, (T*)p, pnew, (T*)q, st, part);
     RW_HIP(hipGetLastError());
@@ -156,8 +162,11 @@ template <typename V, typename T>
 static rw_status apply_op(rw_context* ctx, const rw_volume* vol, const WCoef& wc, const void* p,
                           void* q, void* ws, int precision) {
     const TileChoice tc = choose_tiles(make_geom(vol->dims), precision, 1);
-    if (tc.by == 8) return apply_op_by<V, T, 8>(ctx, vol, wc, tc, p, q, ws);
-    return apply_op_by<V, T, 4>(ctx, vol, wc, tc, p, q, ws);
+    if constexpr (std::is_same<T, float>::value) {
+        if (tc.vx == 4) return apply_op_vx<V, T, 4>(ctx, vol, wc, tc, p, q, ws);
+    }
+    if (tc.vx == 2) return apply_op_vx<V, T, 2>(ctx, vol, wc, tc, p, q, ws);
+    return apply_op_vx<V, T, 1>(ctx, vol, wc, tc, p, q, ws);
 }
 
 }  // namespace rw

@@ -18,7 +18,7 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, TileChoice> g_tuned;  // (precision, R, size class)
 thread_local bool g_forced = false;
-thread_local TileChoice g_force{4, 32, 0};
+thread_local TileChoice g_force{4, 32, 0, 1};
 
 int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
@@ -38,10 +38,12 @@ TileChoice tuned_tiles(const Geom& G, int precision, int R) {
         auto it = g_tuned.find(std::make_tuple(precision, R, size_class(G)));
         if (it != g_tuned.end()) return it->second;
     }
-    // measured on MI355X (512^3, two labels): float32 passes prefer the
+    // measured on MI355X (512^3, two labels): two columns per lane (128-wide
+    // tiles) beat one and four in both precisions; float32 passes prefer the
     // XCD-aware tile order, float64 passes the plain one
-    TileChoice c{4, 32, precision == RW_PREC_MIXED ? 1 : 0};
+    TileChoice c{4, 32, precision == RW_PREC_MIXED ? 1 : 0, 2};
     c.by = env_int("RW_TILE_BY", c.by);
+    c.vx = env_int("RW_TILE_VX", c.vx);
     c.zc = env_int("RW_TILE_ZC", c.zc);
     c.xcd = env_int("RW_TILE_XCD", c.xcd);
     if (c.by != 4 && c.by != 8) c.by = 4;
@@ -64,7 +66,7 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
     const Geom G = make_geom(vol->dims);
     const int K = seeds->num_labels;
     const int R = std::max(1, std::min(4, opts->solve_all_labels ? K : K - 1));
-    static const int bys[] = {4, 8};
+    static const int vxs[] = {1, 2, 4};
     static const int zcs[] = {16, 32, 64};
     static const int xcds[] = {0, 1};
     rw_options o = *opts;
@@ -74,11 +76,12 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
     o.x0 = nullptr;
     double best_t = INFINITY;
     TileChoice win = tuned_tiles(G, opts->precision, R);
-    for (int by : bys)
+    for (int vx : vxs)
         for (int zc : zcs)
             for (int xcd : xcds) {
+                if (vx == 4 && opts->precision != RW_PREC_MIXED) continue;
                 g_forced = true;
-                g_force = TileChoice{by, zc, xcd};
+                g_force = TileChoice{4, zc, xcd, vx};
                 rw_stats st;
                 memset(&st, 0, sizeof(st));
                 // every candidate writes the scratch output
@@ -91,7 +94,7 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
                 const double t = (st.pass_ms[0] + st.pass_ms[1]) / double(l);
                 if (t < best_t) {
                     best_t = t;
-                    win = TileChoice{by, zc, xcd};
+                    win = TileChoice{4, zc, xcd, vx};
                 }
             }
     {
@@ -99,7 +102,7 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
         g_tuned[std::make_tuple(opts->precision, R, size_class(G))] = win;
     }
     if (best) {
-        best[0] = win.by;
+        best[0] = win.vx;
         best[1] = win.zc;
         best[2] = win.xcd;
     }

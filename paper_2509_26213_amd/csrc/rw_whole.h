@@ -241,15 +241,18 @@ __global__ __launch_bounds__(256) void k_finish(const uint8_t* __restrict__ lab,
 
 // ================================================================== host
 
-// Tile shape: 64 x BY columns by zc planes.  BY and zc come from the tuning
-// table (rw_tune.hip); zc shrinks until the grid has enough blocks.
+// Tile shape of a whole-volume solve: 64 vx x 4 columns by zc planes; vx
+// and zc come from the tuning table (rw_tune.hip); zc shrinks until the grid
+// has enough blocks.
 inline TileChoice choose_tiles(const Geom& G, int precision, int R) {
     TileChoice c = tuned_tiles(G, precision, R);
-    const int64_t cols = (int64_t)((G.nx + 63) / 64) * ((G.ny + c.by - 1) / c.by);
-    while (c.zc > 4 && cols * ((G.nz + c.zc - 1) / c.zc) < 2048) c.zc = std::max(4, c.zc / 2);
+    c.by = 4;
+    if (c.vx != 2 && c.vx != 4) c.vx = 1;
+    if (precision != RW_PREC_MIXED && c.vx > 2) c.vx = 2;
+    const int64_t cols = (int64_t)((G.nx + 64 * c.vx - 1) / (64 * c.vx)) * ((G.ny + 3) / 4);
+    while (c.zc > 4 && cols * ((G.nz + c.zc - 1) / c.zc) < 1024) c.zc = std::max(4, c.zc / 2);
     // the partial buffers are sized for 64 x 4 x 4 tiles
     c.zc = std::max(4, c.zc);
-    c.by = c.by == 8 ? 8 : 4;
     return c;
 }
 
@@ -281,16 +284,18 @@ inline size_t carve_group(Carver& cv, const Geom& G, int R, bool mixed, GroupBuf
     return cv.bytes();
 }
 
-// Planes per batch of the CG passes: float64 operands need twice the
-// registers, so they batch half as many planes.
-template <typename T>
+// Planes per batch of the CG passes: the registers of a batch hold U x VX
+// values per operand, 4 in float32 and 2 in float64.
+template <typename T, int VX>
 struct PlaneBatch {
-    static constexpr int value = std::is_same<T, double>::value ? 2 : 4;
+    static constexpr int per = std::is_same<T, double>::value ? 2 : 4;
+    static constexpr int value = per / VX > 0 ? per / VX : 1;
 };
 
-template <typename V, typename T, int R, int BY>
+template <typename V, typename T, int R, int VX>
 struct WholeSolve {
-    static constexpr int ZU = PlaneBatch<T>::value;
+    static constexpr int BY = 4;
+    static constexpr int ZU = PlaneBatch<T, VX>::value;
     rw_context* ctx;
     const V* vol;
     const uint8_t* lab;
@@ -327,12 +332,12 @@ struct WholeSolve {
     rw_status launch_iteration(hipEvent_t* ev) {
         hipStream_t s = ctx->s;
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
-        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, wc, ts(), zv,
+        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, VX, WholeTiles>), grid(), block(), 0, s, vol, wc, ts(), zv,
                            p0, p1, (T*)nullptr, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_fin1<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, WholeTiles>), grid(), block(), 0, s, vol, lab, wc, ts(),
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, VX, WholeTiles>), grid(), block(), 0, s, vol, lab, wc, ts(),
                            xv, zv, (const T*)p0, (const T*)p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
         hipLaunchKernelGGL((k_fin2<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st,
@@ -547,18 +552,18 @@ struct WholeSolve {
     }
 };
 
-template <typename V, typename T, int R, int BY>
-inline rw_status run_group_by(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
+template <typename V, typename T, int R, int VX>
+inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                               const rw_options* o, int lab0, const double* x0,
                               const GroupBuffers& B, const TileChoice& tc, void* prob_out,
                               rw_stats* stats, int r_base, int* worst) {
-    WholeSolve<V, T, R, BY> S;
+    WholeSolve<V, T, R, VX> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(vol->data);
     S.lab = lab;
     S.G = make_geom(vol->dims);
     S.wc = make_wcoef(vol, o->beta, o->w_eps);
-    S.tm = make_tilemap(S.G, BY, tc.zc, tc.xcd);
+    S.tm = make_tilemap(S.G, WholeSolve<V, T, R, VX>::BY, tc.zc, tc.xcd, VX);
     S.lab0 = lab0;
     S.mixed = o->precision == RW_PREC_MIXED;
     S.reliable = S.mixed && o->refine_mode == 0;
@@ -599,8 +604,10 @@ inline rw_status run_group_by(rw_context* ctx, const rw_volume* vol, const uint8
         stats->box_voxel_iterations += S.box_vox;
         stats->rhs_voxel_iterations += S.rhs_vox;
         stats->refinements += S.refreshes();
-        stats->tile_by = BY;
+        stats->tile_by = S.tm.by;
         stats->tile_zc = S.tm.zc;
+        stats->tile_vx = VX;
+        stats->tile_xcd = S.tm.xcd;
     }
     if (*worst < 0) return RW_OK;  // caller reports, outputs untouched
     const int64_t n = S.G.n;

@@ -80,13 +80,16 @@ class Stats(ctypes.Structure):
                 ("pass_ms", ctypes.c_double * 2), ("pass_launches", ctypes.c_int64 * 2),
                 ("rhs_iterations", ctypes.c_int64), ("box_voxel_iterations", ctypes.c_int64),
                 ("rhs_voxel_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
-                ("unknowns", ctypes.c_int64)]
+                ("unknowns", ctypes.c_int64), ("tile_vx", ctypes.c_int32),
+                ("tile_xcd", ctypes.c_int32)]
 
     def to_dict(self):
         R = self.num_solved
         return dict(iters=list(self.iters[:R]), label_status=list(self.label_status[:R]),
                     rel_residual=list(self.rel_residual[:R]), num_solved=R,
-                    refinements=self.refinements, tile=(self.tile_by, self.tile_zc),
+                    refinements=self.refinements,
+                    tile=dict(vx=self.tile_vx, by=self.tile_by, zc=self.tile_zc,
+                              xcd=self.tile_xcd),
                     device_ms=self.device_ms,
                     loop_ms=self.loop_ms, pass_ms=list(self.pass_ms),
                     pass_launches=list(self.pass_launches), rhs_iterations=self.rhs_iterations,
@@ -564,7 +567,7 @@ def random_walker(g, beta, labels, K, tol=1e-10, solve_all_labels=False):
 
 
 def autotune(vol, labels, K, beta, precision="mixed", lo=None, hi=None, ctx=None, **kw):
-    """Pick and record the fastest stencil tile shape for this volume; returns (by, zc, xcd)."""
+    """Pick and record the fastest stencil tile shape for this volume; returns (vx, zc, xcd)."""
     import warnings
     ctx = ctx or default_context()
     V = make_volume(vol, lo, hi)
