@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--update-delta", type=float, default=0.1,
+                    help="mixed precision: float64 residual refresh when ||r|| fell by this factor")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--profile-iters", type=int, default=0,
@@ -181,6 +183,8 @@ def main():
         with warnings.catch_warnings():
             if args.profile_iters:
                 warnings.simplefilter("ignore")
+            if precision == "mixed":
+                extra["update_delta"] = args.update_delta
             return rw.solve(vol, lab, K, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
                             ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing,
                             **extra)
@@ -275,6 +279,8 @@ def bench_hier(args):
     (48, 20, 40) classified from the upsampled coarse solution, the uncertain
     ones solved in one batched brick solve (mixed), the others filled.  One
     step = the whole pipeline on the resident volume."""
+    import warnings
+
     import numpy as np
     import torch
     from paper_2509_26213_amd import rw
@@ -301,9 +307,15 @@ def bench_hier(args):
         if ina:
             rw.fill_bricks(coarse, lab, 4, ina, prob)
         t = time.perf_counter()
-        _, iters, bst = rw.solve_bricks(vol, lab, K, case.beta, coarse, 4, act, prob_out=prob,
-                                        tol=1e-6, precision="mixed", return_stats=True,
-                                        kernel_timing=timing, lo=0.0, hi=65535.0)
+        extra = {"max_iter": args.profile_iters} if args.profile_iters else {}
+        extra["update_delta"] = args.update_delta
+        with warnings.catch_warnings():
+            if args.profile_iters:
+                warnings.simplefilter("ignore")
+            _, iters, bst = rw.solve_bricks(vol, lab, K, case.beta, coarse, 4, act,
+                                            prob_out=prob, tol=1e-6, precision="mixed",
+                                            return_stats=True, kernel_timing=timing, lo=0.0,
+                                            hi=65535.0, **extra)
         torch.cuda.synchronize()
         return dict(coarse=cst, bricks=bst, n_active=len(act), n_cand=len(cands),
                     brick_s=time.perf_counter() - t, iters=iters)

@@ -28,7 +28,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v,
 // byte offset (the loads then take the base in scalar registers and only the
 // 32-bit offset per lane).
 template <typename P>
-__device__ __forceinline__ P ld(const P* __restrict__ base, uint32_t i) {
+__device__ __forceinline__ P ldu(const P* __restrict__ base, uint32_t i) {
     return *reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + i * uint32_t(sizeof(P)));
 }
 template <typename P>
@@ -98,8 +98,23 @@ struct BrickTiles {
     const int* list_count;
     int zc, by;
     int ntiles;  // partial stride (all tiles)
-    __device__ __forceinline__ int count() const { return *list_count; }
-    __device__ __forceinline__ bool get(int i, BoxTile& b) const {
+    int xcd;    // 1: XCD-aware order
+    // XCD-aware order: slot `it` runs on XCD it % 8 (the grid is a multiple of
+    // 8 blocks, handed to the XCDs round-robin), and each XCD walks its own
+    // contiguous eighth of the list in order, so the tiles of one brick
+    // (consecutive in the list) meet in one L2.  Plain order: slot = index.
+    __device__ __forceinline__ int count() const {
+        return xcd ? 8 * ((*list_count + 7) / 8) : *list_count;
+    }
+    __device__ __forceinline__ bool get(int it, BoxTile& b) const {
+        int i = it;
+        if (xcd) {
+            const int n = *list_count;
+            const int per = (n + 7) / 8;
+            const int pos = it >> 3;
+            i = (it & 7) * per + pos;
+            if (pos >= per || i >= n) return false;
+        }
         const int g = list[i];
         const int bi = tile_brick[g];
         const BrickGeo B = bricks[bi];
@@ -184,150 +199,6 @@ __device__ __forceinline__ double upsample(const Shell& s, int label, int x, int
     return acc;
 }
 
-// ---------------------------------------------------------------- residual
-
-// Float64 residual r = b - A x64 of the current iterate with float64
-// weights, and the start of a CG run: z = r / d written in T (d from
-// T-precision weights, the ones the passes use).  Dirichlet data of label
-// lab0 + r: 1 on its seeds, 0 on other seeds (lab0 = 0: 0 on every seed),
-// the upsampled coarse value on non-seed shell voxels; rhs (optional) adds an
-// explicit right-hand side.  Partials per tile [4R + 2][ntiles]: per label
-// r.z, r.r (in T), r64.r64, b.b; then the number of unknowns with a
-// non-positive and with a non-finite degree.  mode 0 only measures; mode 1
-// starts a CG run for every label (p buffers and xi zeroed); mode 2
-// refreshes z of the labels flagged for it (st.outer_active == 2).
-template <typename V, typename T, int R, int BY, typename TS>
-__global__ __launch_bounds__(64 * BY) void k_residual(
-    const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
-    Shell sh, int lab0, const double* __restrict__ x64, const double* __restrict__ rhs,
-    T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
-    const RhsState* __restrict__ st, double* __restrict__ part) {
-    constexpr int NQ = 4 * R + 2;
-    const int cnt = ts.count();
-    for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
-        BoxTile bt;
-        if (!ts.get(it, bt)) continue;
-        const Geom& G = bt.G;
-        const V* __restrict__ vol = volp + bt.voff;
-        const uint8_t* __restrict__ lab = labp + bt.voff;
-        int wmask = 0;
-        if (mode == 2) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (st[bt.sidx * R + r].outer_active == 2) wmask |= 1 << r;
-            if (!wmask) continue;
-        }
-        double acc[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-        const int lyb = bt.Y0 + threadIdx.y;
-        for (int sub = 0; sub < bt.tw; sub += 64) {
-            const int lxb = bt.X0 + sub + threadIdx.x;
-            if (lxb >= bt.sx || lyb >= bt.sy) continue;
-            const int gx = bt.ox + lxb, gy = bt.oy + lyb;
-            for (int lz = bt.z0; lz < bt.z1; ++lz) {
-                const int gz = bt.oz + lz;
-                const int64_t c = (int64_t)gz * G.plane + (int64_t)gy * G.nx + gx;
-                const int64_t cb = ((int64_t)lz * bt.sy + lyb) * bt.sx + lxb;
-                const uint8_t lc = lab[c];
-                if (lc != 0) {
-                    if (mode == 1) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const int64_t o = bt.vbase + r * bt.vstride + cb;
-                            zv[o] = T(0);
-                            p0[o] = T(0);
-                            p1[o] = T(0);
-                            if (xi) xi[o] = T(0);
-                        }
-                    }
-                    continue;
-                }
-                // neighbour order -x, +x, -y, +y, -z, +z (the passes sum d in this order)
-                const bool hv[6] = {gx > 0, gx + 1 < G.nx, gy > 0, gy + 1 < G.ny, gz > 0,
-                                    gz + 1 < G.nz};
-                const int64_t nb[6] = {c - 1, c + 1, c - G.nx, c + G.nx, c - G.plane, c + G.plane};
-                const int dxl[6] = {-1, 1, 0, 0, 0, 0}, dyl[6] = {0, 0, -1, 1, 0, 0},
-                          dzl[6] = {0, 0, 0, 0, -1, 1};
-                const double vc = (double)vol[c];
-                double w[6];
-                double d = 0.0;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    w[k] = hv[k] ? Weight<double>::of(vc - (double)vol[nb[k]], wc) : 0.0;
-                    d += w[k];
-                }
-                T dT;
-                if constexpr (std::is_same<T, double>::value) {
-                    dT = d;
-                } else {
-                    const T vcT = (T)vol[c];
-                    T wT[6];
-#pragma unroll
-                    for (int k = 0; k < 6; ++k)
-                        wT[k] = hv[k] ? Weight<T>::of(vcT - (T)vol[nb[k]], wc) : T(0);
-                    dT = wT[0] + wT[1] + wT[2] + wT[3] + wT[4] + wT[5];
-                }
-                uint8_t ln[6];
-                bool inb[6];
-                int64_t nbb[6];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    ln[k] = hv[k] ? lab[nb[k]] : 0;
-                    const int xx = lxb + dxl[k], yy = lyb + dyl[k], zz = lz + dzl[k];
-                    inb[k] = xx >= 0 && xx < bt.sx && yy >= 0 && yy < bt.sy && zz >= 0 && zz < bt.sz;
-                    nbb[k] = ((int64_t)zz * bt.sy + yy) * bt.sx + xx;
-                }
-                if (!(d > 0.0)) acc[4 * R] += 1.0;
-                if (!isfinite(d)) acc[4 * R + 1] += 1.0;
-                const T dinv = T(1) / dT;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int L = lab0 + r;
-                    const int64_t vb = bt.vbase + r * bt.vstride;
-                    const double xc = x64 ? x64[vb + cb] : 0.0;
-                    double b = rhs ? rhs[vb + cb] : 0.0;
-                    double res = b;
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        if (!hv[k]) continue;
-                        double xj;
-                        if (ln[k] != 0) {
-                            xj = (lab0 > 0 && ln[k] == L) ? 1.0 : 0.0;
-                            b += w[k] * xj;
-                        } else if (inb[k]) {
-                            xj = x64 ? x64[vb + nbb[k]] : 0.0;
-                        } else {
-                            xj = (sh.coarse && lab0 > 0)
-                                     ? upsample(sh, L, bt.gox + gx + dxl[k], bt.goy + gy + dyl[k],
-                                                bt.goz + gz + dzl[k])
-                                     : 0.0;
-                            b += w[k] * xj;
-                        }
-                        res += w[k] * (xj - xc);
-                    }
-                    const T rT = (T)res;
-                    const T zval = dinv * rT;
-                    acc[4 * r + 0] += (double)rT * (double)zval;
-                    acc[4 * r + 1] += (double)rT * (double)rT;
-                    acc[4 * r + 2] += res * res;
-                    acc[4 * r + 3] += b * b;
-                    const int64_t o = vb + cb;
-                    if (mode == 1) {
-                        zv[o] = zval;
-                        p0[o] = T(0);
-                        p1[o] = T(0);
-                        if (xi) xi[o] = T(0);
-                    } else if (mode == 2 && (wmask & (1 << r))) {
-                        zv[o] = zval;
-                    }
-                }
-            }
-        }
-        block_sum_store<NQ, BY>(acc, part + bt.pidx, ts.ntiles);
-    }
-}
-
 // ---------------------------------------------------------------- CG passes
 
 template <int BY, int U, int VX>
@@ -340,9 +211,10 @@ struct TileLanes {
     bool in_box[VX], in_vol[VX];      // own column v inside the box / the volume
     uint32_t colv[VX], colb[VX];      // clamped in-plane offsets in the volume / the box
     bool hx_use, hx_vol, hx_box;
-    int hx_k, hx_col_lds;
+    int hx_k, hx_col_lds, hx_gx;
     uint32_t hx_colv, hx_colb;
     bool hy_use[NYH];
+    int hy_gy[NYH];
     bool hy_vol[NYH][VX], hy_box[NYH][VX];
     int hy_k[NYH], hy_row_lds[NYH];
     uint32_t hy_colv[NYH][VX], hy_colb[NYH][VX];
@@ -371,6 +243,7 @@ struct TileLanes {
         hx_use = lx < 2 * U;
         const int hxb = side ? b.X0 + TW : b.X0 - 1;
         const int hgx = b.ox + hxb;
+        hx_gx = hgx;
         hx_vol = hx_use && hgx >= 0 && hgx < G.nx && gy < G.ny;
         hx_box = hx_use && hxb >= 0 && hxb < b.sx && lyb < b.sy;
         hx_colv = uint32_t(cgy) * uint32_t(G.nx) + uint32_t(clampi(hgx, 0, G.nx - 1));
@@ -385,6 +258,7 @@ struct TileLanes {
             hy_k[j] = min(i >> 1, U - 1);
             const int yb = sy ? b.Y0 + BY : b.Y0 - 1;
             const int gyh = b.oy + yb;
+            hy_gy[j] = gyh;
             const uint32_t rv = uint32_t(clampi(gyh, 0, G.ny - 1)) * uint32_t(G.nx);
             const uint32_t rb = uint32_t(clampi(yb, 0, b.sy - 1)) * uint32_t(b.sx);
 #pragma unroll
@@ -504,13 +378,13 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
             const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = (T)ld(vol + om.v, L.colv[v]);
-                Gv[1][v] = (T)ld(vol + oc.v, L.colv[v]);
+                Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
+                Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const T a = ld(zr[r] + om.b, L.colb[v]) + bet[r] * ld(po[r] + om.b, L.colb[v]);
+                    const T a = ldu(zr[r] + om.b, L.colb[v]) + bet[r] * ldu(po[r] + om.b, L.colb[v]);
                     Pv[0][r][v] = om.inb ? a : T(0);
-                    Pv[1][r][v] = ld(zr[r] + oc.b, L.colb[v]) + bet[r] * ld(po[r] + oc.b, L.colb[v]);
+                    Pv[1][r][v] = ldu(zr[r] + oc.b, L.colb[v]) + bet[r] * ldu(po[r] + oc.b, L.colb[v]);
                 }
             }
         }
@@ -533,22 +407,22 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                 nin[k] = o.inb;
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Gv[k + 2][v] = (T)ld(vol + o.v, L.colv[v]);
+                    Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        zN[k][r][v] = ld(zr[r] + o.b, L.colb[v]);
-                        oN[k][r][v] = ld(po[r] + o.b, L.colb[v]);
+                        zN[k][r][v] = ldu(zr[r] + o.b, L.colb[v]);
+                        oN[k][r][v] = ldu(po[r] + o.b, L.colb[v]);
                     }
                 }
             }
             T hxg, hxz[R], hxo[R];
             {
                 const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)ld(vol + o.v, L.hx_colv);
+                hxg = (T)ldu(vol + o.v, L.hx_colv);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    hxz[r] = ld(zr[r] + o.b, L.hx_colb);
-                    hxo[r] = ld(po[r] + o.b, L.hx_colb);
+                    hxz[r] = ldu(zr[r] + o.b, L.hx_colb);
+                    hxo[r] = ldu(po[r] + o.b, L.hx_colb);
                 }
             }
             T hyg[NYH][VX], hyz[NYH][R][VX], hyo[NYH][R][VX];
@@ -557,11 +431,11 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    hyg[j][v] = (T)ld(vol + o.v, L.hy_colv[j][v]);
+                    hyg[j][v] = (T)ldu(vol + o.v, L.hy_colv[j][v]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        hyz[j][r][v] = ld(zr[r] + o.b, L.hy_colb[j][v]);
-                        hyo[j][r][v] = ld(po[r] + o.b, L.hy_colb[j][v]);
+                        hyz[j][r][v] = ldu(zr[r] + o.b, L.hy_colb[j][v]);
+                        hyo[j][r][v] = ldu(po[r] + o.b, L.hy_colb[j][v]);
                     }
                 }
             }
@@ -699,13 +573,13 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
             const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = (T)ld(vol + om.v, L.colv[v]);
-                Gv[1][v] = (T)ld(vol + oc.v, L.colv[v]);
+                Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
+                Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const T a = ld(pr[r] + om.b, L.colb[v]);
+                    const T a = ldu(pr[r] + om.b, L.colb[v]);
                     Pv[0][r][v] = om.inb ? a : T(0);
-                    Pv[1][r][v] = ld(pr[r] + oc.b, L.colb[v]);
+                    Pv[1][r][v] = ldu(pr[r] + oc.b, L.colb[v]);
                 }
             }
         }
@@ -727,26 +601,26 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
                 const PlaneOff oc = plane_off(G, bt, zb + k);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Gv[k + 2][v] = (T)ld(vol + o.v, L.colv[v]);
+                    Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const T a = ld(pr[r] + o.b, L.colb[v]);
+                        const T a = ldu(pr[r] + o.b, L.colb[v]);
                         Pv[k + 2][r][v] = o.inb ? a : T(0);
                     }
-                    Lv[k][v] = ld(lab + oc.v, L.colv[v]);
+                    Lv[k][v] = ldu(lab + oc.v, L.colv[v]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        Xv[k][r][v] = ld(xr[r] + oc.b, L.colb[v]);
-                        Zv[k][r][v] = ld(zr[r] + oc.b, L.colb[v]);
+                        Xv[k][r][v] = ldu(xr[r] + oc.b, L.colb[v]);
+                        Zv[k][r][v] = ldu(zr[r] + oc.b, L.colb[v]);
                     }
                 }
             }
             T hxg, hxp[R];
             {
                 const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)ld(vol + o.v, L.hx_colv);
+                hxg = (T)ldu(vol + o.v, L.hx_colv);
 #pragma unroll
-                for (int r = 0; r < R; ++r) hxp[r] = ld(pr[r] + o.b, L.hx_colb);
+                for (int r = 0; r < R; ++r) hxp[r] = ldu(pr[r] + o.b, L.hx_colb);
             }
             T hyg[NYH][VX], hyp[NYH][R][VX];
 #pragma unroll
@@ -754,9 +628,9 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    hyg[j][v] = (T)ld(vol + o.v, L.hy_colv[j][v]);
+                    hyg[j][v] = (T)ldu(vol + o.v, L.hy_colv[j][v]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) hyp[j][r][v] = ld(pr[r] + o.b, L.hy_colb[j][v]);
+                    for (int r = 0; r < R; ++r) hyp[j][r][v] = ldu(pr[r] + o.b, L.hy_colb[j][v]);
                 }
             }
             __syncthreads();
@@ -834,6 +708,267 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
             }
         }
         block_sum_store<2 * R, BY>(acc, part + bt.pidx, ts.ntiles);
+    }
+}
+
+
+// ---------------------------------------------------------------- residual
+
+// Value of one cell of the full-grid embedding x~ of label lab0 + r for the
+// float64 residual: the iterate on unknowns of the box, 1 on the label's
+// seeds and 0 on other seeds (lab0 = 0: 0 on every seed), the upsampled
+// coarse value on non-seed voxels outside the box (the brick shell), 0
+// outside the volume.  dir: the cell carries Dirichlet data.
+template <int R>
+struct XCell {
+    double g;
+    double xt[R];
+    bool dir;
+
+    __device__ __forceinline__ void make(double gv, uint8_t lb, const double (&xb)[R], bool in_vol,
+                                         bool in_box, const Shell& sh, int lab0, int gx, int gy,
+                                         int gz) {
+        g = in_vol ? gv : 0.0;
+        dir = !(in_box && lb == 0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double v = 0.0;
+            if (!in_vol) v = 0.0;
+            else if (lb != 0) v = (lab0 > 0 && lb == lab0 + r) ? 1.0 : 0.0;
+            else if (in_box) v = xb[r];
+            else if (sh.coarse && lab0 > 0) v = upsample(sh, lab0 + r, gx, gy, gz);
+            xt[r] = v;
+        }
+    }
+};
+
+// Float64 residual r = b - A x64 of the current iterate with float64
+// weights, and the start of a CG run: z = r / d written in T (d from
+// T-precision weights, summed in the passes' order, so the passes rebuild
+// r = d z with the same d).  Dirichlet data as in XCell; rhs (optional) adds
+// an explicit right-hand side.  Partials per tile [4R + 2][ntiles]: per label
+// r.z, r.r (in T), r64.r64, b.b; then the number of unknowns with a
+// non-positive and with a non-finite degree.  mode 0 only measures; mode 1
+// starts a CG run for every label (p buffers and xi zeroed); mode 2
+// refreshes z of the labels flagged for it (st.outer_active == 2).
+// Tiled like the passes (one plane per batch): every cell's x~ is formed once
+// by the lane that loads it and shared through LDS.
+template <typename V, typename T, int R, int BY, int VX, typename TS>
+__global__ __launch_bounds__(64 * BY) void k_residual(
+    const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
+    Shell sh, int lab0, const double* __restrict__ x64, const double* __restrict__ rhs,
+    T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
+    const RhsState* __restrict__ st, double* __restrict__ part) {
+    constexpr int NQ = 4 * R + 2;
+    using Lanes = TileLanes<BY, 1, VX>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int TW = Lanes::TW;
+    __shared__ double sg[BY + 2][TW + 2];
+    __shared__ double sx[R][BY + 2][TW + 2];
+    __shared__ uint8_t sdir[BY + 2][TW + 2];
+    const int cnt = ts.count();
+    for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+        BoxTile bt;
+        if (!ts.get(it, bt)) continue;
+        const Geom& G = bt.G;
+        const V* __restrict__ vol = volp + bt.voff;
+        const uint8_t* __restrict__ lab = labp + bt.voff;
+        int wmask = 0;
+        if (mode == 2) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (st[bt.sidx * R + r].outer_active == 2) wmask |= 1 << r;
+            if (!wmask) continue;  // uniform over the block
+        }
+        Lanes L;
+        L.init(G, bt);
+        const int64_t bplane = (int64_t)bt.sx * bt.sy;
+        double acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+
+        // own column cells of one plane
+        auto own_cells = [&](int lz, XCell<R> (&c)[VX], uint8_t (&lb)[VX]) {
+            const PlaneOff o = plane_off(G, bt, lz);
+            const int gz = bt.oz + lz;
+            const bool zvol = gz >= 0 && gz < G.nz;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const double gv = (double)ldu(vol + o.v, L.colv[v]);
+                lb[v] = ldu(lab + o.v, L.colv[v]);
+                double xb[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.colb[v]) : 0.0;
+                c[v].make(gv, lb[v], xb, L.in_vol[v] && zvol, L.in_box[v] && o.inb, sh, lab0,
+                          bt.gox + L.gx[v], bt.goy + L.gy, bt.goz + gz);
+            }
+        };
+
+        XCell<R> cm[VX], cc[VX], cp[VX];
+        uint8_t lbm[VX], lbc[VX], lbp[VX];
+        own_cells(bt.z0 - 1, cm, lbm);
+        own_cells(bt.z0, cc, lbc);
+        for (int lz = bt.z0; lz < bt.z1; ++lz) {
+            const int gz = bt.oz + lz;
+            const bool zvol = gz >= 0 && gz < G.nz;
+            own_cells(lz + 1, cp, lbp);
+            // halo cells of plane lz
+            const PlaneOff o = plane_off(G, bt, lz);
+            XCell<R> hx;
+            {
+                const double gv = (double)ldu(vol + o.v, L.hx_colv);
+                const uint8_t lb = ldu(lab + o.v, L.hx_colv);
+                double xb[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hx_colb) : 0.0;
+                hx.make(gv, lb, xb, L.hx_vol && zvol, L.hx_box && o.inb, sh, lab0,
+                        bt.gox + L.hx_gx, bt.goy + L.gy, bt.goz + gz);
+            }
+            XCell<R> hy[NYH][VX];
+#pragma unroll
+            for (int j = 0; j < NYH; ++j)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const double gv = (double)ldu(vol + o.v, L.hy_colv[j][v]);
+                    const uint8_t lb = ldu(lab + o.v, L.hy_colv[j][v]);
+                    double xb[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hy_colb[j][v])
+                                    : 0.0;
+                    hy[j][v].make(gv, lb, xb, L.hy_vol[j][v] && zvol, L.hy_box[j][v] && o.inb,
+                                  sh, lab0, bt.gox + L.gx[v], bt.goy + L.hy_gy[j],
+                                  bt.goz + gz);
+                }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const int c = 64 * v + L.lx + 1;
+                sg[L.ly + 1][c] = cc[v].g;
+                sdir[L.ly + 1][c] = cc[v].dir;
+#pragma unroll
+                for (int r = 0; r < R; ++r) sx[r][L.ly + 1][c] = cc[v].xt[r];
+            }
+            if (L.hx_use) {
+                sg[L.ly + 1][L.hx_col_lds] = hx.g;
+                sdir[L.ly + 1][L.hx_col_lds] = hx.dir;
+#pragma unroll
+                for (int r = 0; r < R; ++r) sx[r][L.ly + 1][L.hx_col_lds] = hx.xt[r];
+            }
+#pragma unroll
+            for (int j = 0; j < NYH; ++j)
+                if (L.hy_use[j]) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const int c = 64 * v + L.lx + 1;
+                        sg[L.hy_row_lds[j]][c] = hy[j][v].g;
+                        sdir[L.hy_row_lds[j]][c] = hy[j][v].dir;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) sx[r][L.hy_row_lds[j]][c] = hy[j][v].xt[r];
+                    }
+                }
+            __syncthreads();
+            const bool zin = lz < bt.z1;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                if (!(L.in_box[v] && zin)) continue;
+                const uint32_t cb = L.colb[v];
+                const int64_t ob = (int64_t)lz * bplane;
+                if (lbc[v] != 0) {
+                    if (mode == 1) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int64_t vb = bt.vbase + r * bt.vstride + ob;
+                            stu(zv + vb, cb, T(0));
+                            stu(p0 + vb, cb, T(0));
+                            stu(p1 + vb, cb, T(0));
+                            if (xi) stu(xi + vb, cb, T(0));
+                        }
+                    }
+                    continue;
+                }
+                const int c = 64 * v + L.lx;
+                // neighbour order -x, +x, -y, +y, -z, +z (the passes sum d in this order)
+                const bool hv[6] = {L.gx[v] > 0, L.gx[v] + 1 < G.nx, L.gy > 0, L.gy + 1 < G.ny,
+                                    gz > 0, gz + 1 < G.nz};
+                const int ry[6] = {L.ly + 1, L.ly + 1, L.ly, L.ly + 2, 0, 0};
+                const int rx[6] = {c, c + 2, c + 1, c + 1, 0, 0};
+                double gn[6];
+                bool dn[6];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gn[k] = sg[ry[k]][rx[k]];
+                    dn[k] = sdir[ry[k]][rx[k]] != 0;
+                }
+                gn[4] = cm[v].g;
+                dn[4] = cm[v].dir;
+                gn[5] = cp[v].g;
+                dn[5] = cp[v].dir;
+                const double gc = cc[v].g;
+                double w[6];
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    w[k] = hv[k] ? Weight<double>::of(gc - gn[k], wc) : 0.0;
+                    d += w[k];
+                }
+                T dT;
+                if constexpr (std::is_same<T, double>::value) {
+                    dT = d;
+                } else {
+                    T wT[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        wT[k] = hv[k] ? Weight<T>::of((T)gc - (T)gn[k], wc) : T(0);
+                    dT = wT[0] + wT[1] + wT[2] + wT[3] + wT[4] + wT[5];
+                }
+                if (!(d > 0.0)) acc[4 * R] += 1.0;
+                if (!isfinite(d)) acc[4 * R + 1] += 1.0;
+                const T dinv = T(1) / dT;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t vb = bt.vbase + r * bt.vstride + ob;
+                    double xn[6];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) xn[k] = sx[r][ry[k]][rx[k]];
+                    xn[4] = cm[v].xt[r];
+                    xn[5] = cp[v].xt[r];
+                    const double xc = cc[v].xt[r];
+                    double b = rhs ? ldu(rhs + vb, cb) : 0.0;
+                    double res = b;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        if (!hv[k]) continue;
+                        if (dn[k]) b += w[k] * xn[k];
+                        res += w[k] * (xn[k] - xc);
+                    }
+                    const T rT = (T)res;
+                    const T zval = dinv * rT;
+                    acc[4 * r + 0] += (double)rT * (double)zval;
+                    acc[4 * r + 1] += (double)rT * (double)rT;
+                    acc[4 * r + 2] += res * res;
+                    acc[4 * r + 3] += b * b;
+                    if (mode == 1) {
+                        stu(zv + vb, cb, zval);
+                        stu(p0 + vb, cb, T(0));
+                        stu(p1 + vb, cb, T(0));
+                        if (xi) stu(xi + vb, cb, T(0));
+                    } else if (mode == 2 && (wmask & (1 << r))) {
+                        stu(zv + vb, cb, zval);
+                    }
+                }
+            }
+            // carry planes lz, lz+1
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                cm[v] = cc[v];
+                cc[v] = cp[v];
+                lbc[v] = lbp[v];
+            }
+        }
+        block_sum_store<NQ, BY>(acc, part + bt.pidx, ts.ntiles);
     }
 }
 

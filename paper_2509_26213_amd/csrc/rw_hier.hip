@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Shell sh, int
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
-        ts.get(it, bt);
+        if (!ts.get(it, bt)) continue;
         const int lxb = bt.X0 + (threadIdx.x & 63), lyb = bt.Y0 + (threadIdx.x >> 6);
         for (int yy = lyb; yy < min(bt.Y0 + ts.by, bt.sy); yy += 4) {
             if (lxb >= bt.sx) break;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts,
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
-        ts.get(it, bt);
+        if (!ts.get(it, bt)) continue;
         int mask = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void k_brick_write(BrickTiles ts, Geom F,
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
-        ts.get(it, bt);
+        if (!ts.get(it, bt)) continue;
         const int lxb = bt.X0 + (threadIdx.x & 63);
         for (int yy = bt.Y0 + (threadIdx.x >> 6); yy < min(bt.Y0 + ts.by, bt.sy); yy += 4) {
             if (lxb >= bt.sx) break;
@@ -618,15 +618,6 @@ static size_t carve_bricks(Carver& cv, const BrickPlan& P, int R, bool mixed, Br
     return cv.bytes();
 }
 
-static TileChoice brick_tiles(int precision) {
-    Geom G;
-    memset(&G, 0, sizeof(G));
-    TileChoice c = tuned_tiles(G, precision, 0);
-    c.by = c.by == 8 ? 8 : 4;
-    c.zc = std::max(4, c.zc);
-    return c;
-}
-
 template <typename V, typename T, int R, int BY>
 struct BrickSolve {
     static constexpr int ZU = PlaneBatch<T, 1>::value;
@@ -638,7 +629,7 @@ struct BrickSolve {
     Shell sh;
     const rw_options* o;
     bool mixed;
-    int lab0, zc, nb;
+    int lab0, zc, nb, xcd = 0;
     BrickPlan* P;
     BrickBuffers B;
     int grid;
@@ -655,6 +646,7 @@ struct BrickSolve {
         t.list_count = count;
         t.zc = zc;
         t.by = BY;
+        t.xcd = xcd;
         t.ntiles = P->ntiles;
         return t;
     }
@@ -727,7 +719,7 @@ struct BrickSolve {
         const BrickTiles tr = ref();
         hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, lab, B.st,
                            B.x64, (T*)B.xi, 0);
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, tr, sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, (T*)B.xi, 2, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_refresh<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo,
@@ -751,7 +743,7 @@ struct BrickSolve {
         // x0 = upsampled coarse solution, then the brick residuals
         hipLaunchKernelGGL((k_brick_init<T, R>), dim3(grid), dim3(256), 0, s, all(), sh, lab0, lab,
                            B.x64, mixed ? (T*)B.xi : (T*)nullptr);
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, all(), sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, mixed ? (T*)B.xi : (T*)nullptr, 1, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_init<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st,
@@ -853,9 +845,10 @@ static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_see
     S.mixed = mixed;
     S.lab0 = lab0;
     S.zc = tc.zc;
+    S.xcd = tc.brick_xcd;
     S.nb = n_bricks;
     S.P = &P;
-    S.grid = std::max(1, std::min(P.ntiles, 2048));
+    S.grid = 8 * ((std::max(1, std::min(P.ntiles, 2048)) + 7) / 8);  // multiple of 8 (XCD order)
     Carver cv(ws);
     carve_bricks(cv, P, R, mixed, &S.B);
     rw_status e = S.run();
@@ -895,6 +888,8 @@ static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_see
         stats->refinements = int32_t(std::min<int64_t>(refreshes, INT32_MAX));
         stats->tile_by = BY;
         stats->tile_zc = tc.zc;
+        stats->tile_vx = 1;
+        stats->tile_xcd = tc.brick_xcd;
     }
     if (worst < 0) set_error(std::string("brick solve failed: ") + rw_status_string((rw_status)worst));
     return (rw_status)worst;
@@ -907,6 +902,8 @@ static rw_status bricks_by(rw_context* ctx, const rw_volume* fine, const rw_seed
     const TileChoice tc = brick_tiles(o->precision);
     if (tc.by == 8)
         return bricks_run<V, T, R, 8>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
+    if (tc.by == 16)
+        return bricks_run<V, T, R, 16>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
     return bricks_run<V, T, R, 4>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
 }
 

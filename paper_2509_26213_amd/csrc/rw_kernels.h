@@ -26,8 +26,11 @@ rw_status ensure_dev_small(rw_context* ctx, size_t bytes);
 // by in {4, 8}.
 struct TileChoice {
     int by, zc, xcd, vx;
+    int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist
 };
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
+// Tile shape of batched brick solves (vx = 1; by in {4, 8, 16}).
+TileChoice brick_tiles(int precision);
 
 // Sum NQ per-thread values over a block of NW waves in a fixed order (wave
 // butterfly, then the wave totals in wave order); threads 0..NQ-1 write

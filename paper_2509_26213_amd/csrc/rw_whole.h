@@ -357,7 +357,7 @@ struct WholeSolve {
     rw_status launch_residual(int mode) {
         Shell none;
         memset(&none, 0, sizeof(none));
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, WholeTiles>), grid(), block(), 0, ctx->s, vol, lab,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, VX, WholeTiles>), grid(), block(), 0, ctx->s, vol, lab,
                            wc, ts(), none, lab0, B.x64, rhs, zv, p0, p1,
                            mixed ? (T*)B.xi : (T*)nullptr, mode, B.st, B.part);
         RW_HIP(hipGetLastError());

@@ -110,6 +110,36 @@ def test_brick_solves_match_oracle(rw, case, coarse_ref, precision):
                 assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
 
 
+@pytest.mark.parametrize("by,zc,xcd", [(4, 16, 0), (8, 64, 0), (16, 8, 1), (8, 5, 1)])
+def test_brick_tile_shapes_match_oracle(rw, case, coarse_ref, monkeypatch, by, zc, xcd):
+    """Every brick tile shape (rows per block, planes per tile, worklist
+    order) gives the oracle's brick solutions: ragged 32^3 bricks clipped by
+    the volume border, float64."""
+    g, _, _, coarse = coarse_ref
+    monkeypatch.setenv("RW_BRICK_BY", str(by))
+    monkeypatch.setenv("RW_BRICK_ZC", str(zc))
+    monkeypatch.setenv("RW_BRICK_XCD", str(xcd))
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, (32, 32, 32), (5, 3, 7))
+    act = [b for b, a in zip(cands, active) if a][:6]
+    prob, iters, st = rw.solve_bricks(dev(case.vol), dev(case.labels), 3, case.beta, dev(coarse), 4,
+                                      act, tol=1e-6, precision="fp64", return_stats=True)
+    assert st["status"] == 0 and st["tile"]["by"] == by
+    P = host(prob)
+    for (o, s), it in zip(act, iters):
+        o, s = tuple(o), tuple(s)
+        Pf = _up(coarse, case.shape, 4, tuple(np.array(o) - 1), tuple(np.array(s) + 2))
+
+        def shell_value(lab, zz, yy, xx, Pf=Pf, o=o):
+            return Pf[lab - 1][zz - o[0] + 1, yy - o[1] + 1, xx - o[2] + 1]
+
+        xb, info = O.solve_brick(g, case.labels, o, s, shell_value, Pf[:, 1:-1, 1:-1, 1:-1],
+                                 case.beta, tol=1e-6)
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        assert_parity(P[:, sl[0], sl[1], sl[2]], xb, what=f"brick {o} tile {by}x{zc}")
+        for r in range(2):
+            assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
+
+
 def test_bricks_untouched_outside(rw, case, coarse_ref):
     import torch
     _, _, _, coarse = coarse_ref
