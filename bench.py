@@ -73,9 +73,10 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (profiles/<kernel>_<workload>_traffic.md), or None when it is missing or
-    was taken on another version of the kernel source."""
+    """Ratio of measured HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
+    by a copy kernel of known size) to algorithmic bytes per launch, from the
+    committed summary profiles/<kernel>_<workload>_traffic.md; None when it is
+    missing or was taken on another version of the kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -88,9 +89,15 @@ def measured_traffic(kernel, workload):
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["traffic_over_algorithmic"])
     except (KeyError, ValueError):
         return None
+
+
+def traffic(ratio, alg_bytes_per_launch):
+    """HBM bytes per launch: the measured traffic ratio times this run's
+    algorithmic bytes per launch (None without a current measurement)."""
+    return None if ratio is None else ratio * alg_bytes_per_launch
 
 
 def copy_calibration():
@@ -249,7 +256,8 @@ def main():
                    "voxels": n_vox, "labels": K, "solved_labels": s["num_solved"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass2", "achieved": ach2,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_cg_pass2", case.name),
+                     "traffic": traffic(measured_traffic("k_cg_pass2", case.name),
+                                        bytes2 / max(launches2, 1)),
                      "avg_launch_us": ms2 * 1e3 / max(launches2, 1),
                      "bytes_per_launch": bytes2 / max(launches2, 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
@@ -353,8 +361,10 @@ def bench_hier(args):
                    "refreshes": b["refinements"]},
         "roofline": {"bound": "hbm", "kernel": "k_cg_pass2 (bricks)", "achieved": ach2,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_cg_pass2", "hier1024"),
-                     "avg_launch_us": b["pass_ms"][1] * 1e3 / max(b["pass_launches"][1], 1)},
+                     "traffic": traffic(measured_traffic("k_cg_pass2", "hier1024"),
+                                        bytes2 / max(b["pass_launches"][1], 1)),
+                     "avg_launch_us": b["pass_ms"][1] * 1e3 / max(b["pass_launches"][1], 1),
+                     "bytes_per_launch": bytes2 / max(b["pass_launches"][1], 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((b["pass_ms"][0] + b["pass_ms"][1]) * 1e-3)
         / 1e9 / HBM_PEAK_GBS,
