@@ -163,6 +163,14 @@ const char* rw_status_string(rw_status s);
 const char* rw_last_error(void);
 void rw_default_options(rw_options* opts);
 
+/* Output assembly (the segmentation is the label of highest probability,
+ * Sec. IV-B): labels_out[i] = argmax over L of prob[L-1][i], lowest label on
+ * ties.  prob: device [K][n] float32 (RW_DT_F32) or float64 (RW_DT_F64);
+ * labels_out: device uint8 [n], values 1..K.  Invalid arguments return
+ * RW_ERR_INVALID_ARG before any device work. */
+rw_status rw_argmax(rw_context* ctx, const void* prob, int32_t dtype, int32_t num_labels,
+                    int64_t n, uint8_t* labels_out, void* stream);
+
 /* Normalisation range (min, max) of a volume, computed on the device.
  * lo_hi: host, 2 doubles.  NaN in the volume -> RW_ERR_NONFINITE. */
 rw_status rw_minmax(rw_context* ctx, const rw_volume* vol, double* lo_hi, void* stream);

@@ -1,3 +1,4 @@
+#include <algorithm>
 // Context, status strings, options, small reductions (minmax, label counts)
 // and the materialised-weights kernel of librw.so.
 #include <cmath>
@@ -225,6 +226,26 @@ rw_status ensure_events(rw_context* ctx, size_t n) {
     return RW_OK;
 }
 
+
+// Label of the highest probability per voxel, lowest label on ties, from K
+// planar probability arrays.
+template <typename P>
+__global__ __launch_bounds__(256) void k_argmax(const P* __restrict__ prob, int K, int64_t n,
+                                                uint8_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
+        P best = prob[i];
+        int arg = 1;
+        for (int L = 2; L <= K; ++L) {
+            const P v = prob[(int64_t)(L - 1) * n + i];
+            if (v > best) {
+                best = v;
+                arg = L;
+            }
+        }
+        out[i] = uint8_t(arg);
+    }
+}
+
 }  // namespace rw
 
 using namespace rw;
@@ -339,6 +360,26 @@ rw_status rw_minmax(rw_context* ctx, const rw_volume* vol, double* lo_hi, void* 
     lo_hi[0] = h[0];
     lo_hi[1] = h[1];
     return RW_OK;
+}
+
+rw_status rw_argmax(rw_context* ctx, const void* prob, int32_t dtype, int32_t num_labels,
+                    int64_t n, uint8_t* labels_out, void* stream) {
+    if (!ctx || !prob || !labels_out) return invalid("NULL argument");
+    if (num_labels < 1 || num_labels > 255) return invalid("num_labels must be in [1, 255]");
+    if (n < 0) return invalid("n must be >= 0");
+    if (dtype != RW_DT_F32 && dtype != RW_DT_F64) return invalid("probabilities must be f32 or f64");
+    if (n == 0) return RW_OK;
+    rw_status st = stream_enter(ctx, stream);
+    if (st) return st;
+    const dim3 grid(unsigned(std::min<int64_t>((n + 255) / 256, 8192)));
+    if (dtype == RW_DT_F32)
+        hipLaunchKernelGGL(k_argmax<float>, grid, dim3(256), 0, ctx->s, (const float*)prob,
+                           num_labels, n, labels_out);
+    else
+        hipLaunchKernelGGL(k_argmax<double>, grid, dim3(256), 0, ctx->s, (const double*)prob,
+                           num_labels, n, labels_out);
+    RW_HIP(hipGetLastError());
+    return stream_leave(ctx, stream);
 }
 
 rw_status rw_build_weights(rw_context* ctx, const rw_volume* vol, double beta, double w_eps,

@@ -37,7 +37,7 @@ EXPORTS = [
     "rw_default_options", "rw_minmax", "rw_build_weights", "rw_operator_workspace_bytes",
     "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
-    "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune",
+    "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_argmax",
 ]
 
 
@@ -156,6 +156,7 @@ def lib():
     L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                                     ctypes.POINTER(Options), I32, P, P, P, ctypes.POINTER(D), P,
                                     SZ, ctypes.POINTER(Stats), P]
+    L.rw_argmax.argtypes = [P, P, I32, I32, ctypes.c_int64, P, P]
     L.rw_autotune.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                               ctypes.POINTER(Options), P, P, SZ, ctypes.POINTER(I32), P]
     for name in EXPORTS:
@@ -564,6 +565,20 @@ def random_walker(g, beta, labels, K, tol=1e-10, solve_all_labels=False):
     if not torch.is_tensor(beta):
         beta = torch.tensor(float(beta), dtype=torch.float64, device=g.device)
     return RandomWalkerFn.apply(g, beta, labels, K, tol, solve_all_labels)
+
+
+def argmax(prob, out=None, ctx=None):
+    """Label (1..K) of the highest probability per voxel of prob [K][...]
+    (float32 or float64, device), lowest label on ties; uint8 [...]."""
+    ctx = ctx or default_context()
+    prob = prob.contiguous()
+    K = int(prob.shape[0])
+    if out is None:
+        out = torch.empty(tuple(prob.shape[1:]), dtype=torch.uint8, device=prob.device)
+    n = prob[0].numel()
+    _check(lib().rw_argmax(ctx.handle, _ptr(prob), _dt_code(prob), K, n, _ptr(out), _stream()),
+           "rw_argmax")
+    return out
 
 
 def autotune(vol, labels, K, beta, precision="mixed", lo=None, hi=None, ctx=None, **kw):

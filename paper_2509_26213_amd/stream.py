@@ -18,8 +18,9 @@ librw.so call; this module only moves buffers and sequences calls):
 5. certain bricks: rw_fill_bricks of the upsampled coarse probabilities into
    a device brick buffer, D2H.
 
-Output: float32 probabilities [K][nz][ny][nx] in (pinned or plain) host
-memory.  The PCIe traffic is reported separately from the solves.
+Output: float32 probabilities [K][nz][ny][nx] and/or the uint8 label map
+(rw_argmax on the device, only labels cross PCIe) in host memory.  The PCIe
+traffic is reported separately from the solves.
 """
 from __future__ import annotations
 
@@ -43,11 +44,13 @@ def _brick_grid(shape, brick):
 
 def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, tol=1e-6,
                    levels=2, lo=0.0, hi=65535.0, lo_thr=0.02, hi_thr=0.98, precision="mixed",
-                   out=None, ctx=None):
+                   out=None, labels_out=None, ctx=None):
     """vol_host: uint16 or float32 numpy [nz][ny][nx]; lab_host: uint8 numpy.
 
     Brick sizes must be even (level-1 blocks must not straddle bricks).
-    Returns (prob_host float32 [K][...], info dict with timings and counts).
+    out: float32 [K][...] host array for the probabilities; labels_out: uint8
+    [...] host array for the label map.  With neither given, probabilities
+    are returned.  Returns (out, info dict with timings and counts).
     """
     assert all(b % 2 == 0 for b in brick), "brick sizes must be even"
     ctx = ctx or rw.default_context()
@@ -114,7 +117,7 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
     ina = [b for b, a in zip(cands, active) if not a]
     info["bricks"] = len(cands)
     info["active_bricks"] = len(act)
-    if out is None:
+    if out is None and labels_out is None:
         out = np.empty((K,) + shape, dtype=np.float32)
 
     # ---- certain bricks: upsampled coarse probabilities (labels only are streamed)
@@ -134,11 +137,17 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
             local.append(((0, 0, 0), s))
         rw.fill_bricks(coarse, fl, f, local, fp, subvols=subs, ctx=ctx)
         fv = fp.view(K, -1)
+        am = rw.argmax(fv, ctx=ctx) if labels_out is not None else None
         for j, (o, s) in enumerate(chunk):
             n = int(np.prod(s))
-            out[:, o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]] = \
-                fv[:, j * bvox:j * bvox + n].reshape((K,) + tuple(s)).cpu().numpy()
-            info["d2h_bytes"] += K * n * 4
+            sl = (slice(o[0], o[0] + s[0]), slice(o[1], o[1] + s[1]), slice(o[2], o[2] + s[2]))
+            if out is not None:
+                out[(slice(None),) + sl] = fv[:, j * bvox:j * bvox + n].reshape(
+                    (K,) + tuple(s)).cpu().numpy()
+                info["d2h_bytes"] += K * n * 4
+            if am is not None:
+                labels_out[sl] = am[j * bvox:j * bvox + n].reshape(tuple(s)).cpu().numpy()
+                info["d2h_bytes"] += n
     torch.cuda.synchronize()
     info["fill_s"] = time.perf_counter() - t0
 
@@ -197,12 +206,22 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
         meta.append(bst)
         # brick interiors back to the host
         pv = P["p"].view(K, -1)
+        am = rw.argmax(pv, ctx=ctx) if labels_out is not None else None
         for (off, dims, lo_), (ob, s) in zip(subs, bricks_local):
-            blk = pv[:, off:off + int(np.prod(dims))].view((K,) + dims)
-            inner = blk[:, ob[0]:ob[0] + s[0], ob[1]:ob[1] + s[1], ob[2]:ob[2] + s[2]]
+            n = int(np.prod(dims))
             g0 = tuple(lo_[a] + ob[a] for a in range(3))
-            out[:, g0[0]:g0[0] + s[0], g0[1]:g0[1] + s[1], g0[2]:g0[2] + s[2]] = inner.cpu().numpy()
-            info["d2h_bytes"] += inner.numel() * 4
+            dst = (slice(g0[0], g0[0] + s[0]), slice(g0[1], g0[1] + s[1]),
+                   slice(g0[2], g0[2] + s[2]))
+            src = (slice(ob[0], ob[0] + s[0]), slice(ob[1], ob[1] + s[1]),
+                   slice(ob[2], ob[2] + s[2]))
+            if out is not None:
+                inner = pv[:, off:off + n].view((K,) + dims)[(slice(None),) + src]
+                out[(slice(None),) + dst] = inner.cpu().numpy()
+                info["d2h_bytes"] += inner.numel() * 4
+            if am is not None:
+                inner = am[off:off + n].view(dims)[src]
+                labels_out[dst] = inner.cpu().numpy()
+                info["d2h_bytes"] += inner.numel()
         P["done"].record(main)
     torch.cuda.synchronize()
     info["bricks_s"] = time.perf_counter() - t0
@@ -210,6 +229,6 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
     info["brick_iters"] = iters_all
     info["brick_stats"] = meta
     info["total_s"] = time.perf_counter() - t_all
-    return out, info
+    return (out if out is not None else labels_out), info
 
 

@@ -34,6 +34,32 @@ def test_streamed_equals_resident(rw):
     assert info["h2d_bytes"] > c.vol.nbytes
 
 
+def test_streamed_labels_only(rw):
+    """Labels-only output (device argmax, uint8 over PCIe) equals the argmax
+    of the streamed probabilities, lowest label on ties."""
+    from paper_2509_26213_amd.stream import streamed_solve
+    c = blob_case(shape=(40, 70, 66), n_blobs=6, K=3, seeds_per_label=30, sigma=0.06, rmin=5,
+                  rmax=12, seed=43, dtype="u16")
+    prob, _ = streamed_solve(c.vol, c.labels, 3, c.beta, brick=(16, 32, 32), pool=4,
+                             tol=1e-6, levels=2, precision="mixed")
+    lab = np.zeros(c.shape, np.uint8)
+    lab_s, info = streamed_solve(c.vol, c.labels, 3, c.beta, brick=(16, 32, 32), pool=4,
+                                 tol=1e-6, levels=2, precision="mixed", labels_out=lab)
+    assert lab_s is lab
+    assert np.array_equal(lab, (np.argmax(prob, axis=0) + 1).astype(np.uint8))
+    seeded = c.labels > 0
+    assert np.array_equal(lab[seeded], c.labels[seeded])
+
+
+def test_argmax_ties_and_dtypes(rw):
+    import torch
+    rng = np.random.default_rng(5)
+    for dt in (torch.float32, torch.float64):
+        p = rng.integers(0, 3, size=(4, 1000)).astype(np.float64)  # many ties
+        am = host(rw.argmax(torch.tensor(p, dtype=dt, device="cuda")))
+        assert np.array_equal(am, (np.argmax(p, axis=0) + 1).astype(np.uint8))
+
+
 def test_pool_bricks_match_resident_bricks(rw):
     """A brick solved inside its own halo sub-volume equals the same brick
     solved inside the full volume (bitwise)."""
