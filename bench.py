@@ -148,8 +148,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--pool", type=int, default=256,
                     help="stream2048: bricks per device pool")
-    ap.add_argument("--update-delta", type=float, default=0.1,
-                    help="mixed precision: float64 residual refresh when ||r|| fell by this factor")
+    ap.add_argument("--update-delta", type=float, default=None,
+                    help="mixed precision: float64 residual refresh when ||r|| fell by this "
+                         "factor (default: the library's, 0.1 whole volumes, 0.01 bricks)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--profile-iters", type=int, default=0,
@@ -194,7 +195,7 @@ def main():
         with warnings.catch_warnings():
             if args.profile_iters:
                 warnings.simplefilter("ignore")
-            if precision == "mixed":
+            if precision == "mixed" and args.update_delta is not None:
                 extra["update_delta"] = args.update_delta
             return rw.solve(vol, lab, K, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
                             ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing,

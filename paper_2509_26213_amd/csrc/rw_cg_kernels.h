@@ -201,74 +201,88 @@ __device__ __forceinline__ double upsample(const Shell& s, int label, int x, int
 
 // ---------------------------------------------------------------- CG passes
 
-template <int BY, int U, int VX>
+// Lane geometry of a tile.  Each lane owns VX cells per plane: VX columns 64
+// apart (YM = false: the tile is 64 VX x BY columns) or VX rows BY apart
+// (YM = true: 64 x BY VX, for 64-wide boxes).  lr/lc: the cells' LDS row and
+// column (one halo row/column on each side).
+template <int BY, int U, int VX, bool YM = false>
 struct TileLanes {
+    static constexpr int TR = YM ? BY * VX : BY;  // tile rows
+    static constexpr int TC = YM ? 64 : 64 * VX;  // tile columns
+    static constexpr int HR = YM ? VX : 1;        // rows per lane
+    static constexpr int HV = YM ? 1 : VX;        // columns per lane
     static constexpr int NYH = (2 * U + BY - 1) / BY;  // y-halo rows per wave per batch
-    static constexpr int TW = 64 * VX;                 // tile width
+    static constexpr int TW = TC;
     int lx, ly;
-    int gy;                           // own row, global
-    int gx[VX];                       // own columns, global
-    bool in_box[VX], in_vol[VX];      // own column v inside the box / the volume
+    int gx[VX], gy[VX];               // own cells, global column / row
+    int lr[VX], lc[VX];               // own cells in LDS
+    bool in_box[VX], in_vol[VX];      // own cell's column inside the box / the volume
     uint32_t colv[VX], colb[VX];      // clamped in-plane offsets in the volume / the box
     bool hx_use, hx_vol, hx_box;
-    int hx_k, hx_col_lds, hx_gx;
+    int hx_k, hx_col_lds, hx_row_lds, hx_gx, hx_gy;
     uint32_t hx_colv, hx_colb;
     bool hy_use[NYH];
     int hy_gy[NYH];
-    bool hy_vol[NYH][VX], hy_box[NYH][VX];
+    bool hy_vol[NYH][HV], hy_box[NYH][HV];
     int hy_k[NYH], hy_row_lds[NYH];
-    uint32_t hy_colv[NYH][VX], hy_colb[NYH][VX];
+    uint32_t hy_colv[NYH][HV], hy_colb[NYH][HV];
 
     __device__ __forceinline__ void init(const Geom& G, const BoxTile& b) {
         lx = threadIdx.x;
         ly = threadIdx.y;
-        const int lyb = b.Y0 + ly;
-        gy = b.oy + lyb;
-        const int cgy = min(gy, G.ny - 1), cby = min(lyb, b.sy - 1);
-        int cgx[VX], cbx[VX], lxb[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            lxb[v] = b.X0 + 64 * v + lx;
-            gx[v] = b.ox + lxb[v];
-            in_box[v] = lxb[v] < b.sx && lyb < b.sy;
-            in_vol[v] = gx[v] < G.nx && gy < G.ny;
-            cgx[v] = min(gx[v], G.nx - 1);
-            cbx[v] = min(lxb[v], b.sx - 1);
-            colv[v] = uint32_t(cgy) * uint32_t(G.nx) + uint32_t(cgx[v]);
-            colb[v] = uint32_t(cby) * uint32_t(b.sx) + uint32_t(cbx[v]);
+            const int xl = b.X0 + lx + (YM ? 0 : 64 * v);  // box-local
+            const int yl = b.Y0 + ly + (YM ? BY * v : 0);
+            gx[v] = b.ox + xl;
+            gy[v] = b.oy + yl;
+            lr[v] = ly + 1 + (YM ? BY * v : 0);
+            lc[v] = lx + 1 + (YM ? 0 : 64 * v);
+            in_box[v] = xl < b.sx && yl < b.sy;
+            in_vol[v] = gx[v] < G.nx && gy[v] < G.ny;
+            colv[v] = uint32_t(min(gy[v], G.ny - 1)) * uint32_t(G.nx) + uint32_t(min(gx[v], G.nx - 1));
+            colb[v] = uint32_t(min(yl, b.sy - 1)) * uint32_t(b.sx) + uint32_t(min(xl, b.sx - 1));
         }
-        // x halo: lanes 0 .. 2U-1, one value each (side = lane parity, plane = lane / 2)
+        // x halo: lanes 0 .. 2 U HR - 1, one value each: side = lane parity,
+        // plane = (lane / 2) % U, own row = (lane / 2) / U
         const int side = lx & 1;
-        hx_k = min(lx >> 1, U - 1);
-        hx_use = lx < 2 * U;
-        const int hxb = side ? b.X0 + TW : b.X0 - 1;
-        const int hgx = b.ox + hxb;
-        hx_gx = hgx;
-        hx_vol = hx_use && hgx >= 0 && hgx < G.nx && gy < G.ny;
-        hx_box = hx_use && hxb >= 0 && hxb < b.sx && lyb < b.sy;
-        hx_colv = uint32_t(cgy) * uint32_t(G.nx) + uint32_t(clampi(hgx, 0, G.nx - 1));
-        hx_colb = uint32_t(cby) * uint32_t(b.sx) + uint32_t(clampi(hxb, 0, b.sx - 1));
-        hx_col_lds = side ? TW + 1 : 0;
-        // y halo: 2U rows (side, plane) spread over the waves, TW values each
+        const int t = lx >> 1;
+        hx_use = lx < 2 * U * HR;
+        hx_k = min(t % U, U - 1);
+        const int vr = min(t / U, HR - 1);
+        const int yl = b.Y0 + ly + (YM ? BY * vr : 0);
+        const int xl = side ? b.X0 + TC : b.X0 - 1;
+        hx_gx = b.ox + xl;
+        hx_gy = b.oy + yl;
+        hx_vol = hx_use && hx_gx >= 0 && hx_gx < G.nx && hx_gy < G.ny;
+        hx_box = hx_use && xl >= 0 && xl < b.sx && yl < b.sy;
+        hx_colv = uint32_t(min(hx_gy, G.ny - 1)) * uint32_t(G.nx) +
+                  uint32_t(clampi(hx_gx, 0, G.nx - 1));
+        hx_colb = uint32_t(min(yl, b.sy - 1)) * uint32_t(b.sx) + uint32_t(clampi(xl, 0, b.sx - 1));
+        hx_col_lds = side ? TC + 1 : 0;
+        hx_row_lds = ly + 1 + (YM ? BY * vr : 0);
+        // y halo: 2U rows (side, plane) spread over the waves, TC values each
 #pragma unroll
         for (int j = 0; j < NYH; ++j) {
             const int i = ly + j * BY;
             hy_use[j] = i < 2 * U;
             const int sy = i & 1;
             hy_k[j] = min(i >> 1, U - 1);
-            const int yb = sy ? b.Y0 + BY : b.Y0 - 1;
-            const int gyh = b.oy + yb;
+            const int ybl = sy ? b.Y0 + TR : b.Y0 - 1;
+            const int gyh = b.oy + ybl;
             hy_gy[j] = gyh;
             const uint32_t rv = uint32_t(clampi(gyh, 0, G.ny - 1)) * uint32_t(G.nx);
-            const uint32_t rb = uint32_t(clampi(yb, 0, b.sy - 1)) * uint32_t(b.sx);
+            const uint32_t rb = uint32_t(clampi(ybl, 0, b.sy - 1)) * uint32_t(b.sx);
 #pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                hy_vol[j][v] = hy_use[j] && gyh >= 0 && gyh < G.ny && gx[v] < G.nx;
-                hy_box[j][v] = hy_use[j] && yb >= 0 && yb < b.sy && lxb[v] < b.sx;
-                hy_colv[j][v] = rv + uint32_t(cgx[v]);
-                hy_colb[j][v] = rb + uint32_t(cbx[v]);
+            for (int h = 0; h < HV; ++h) {
+                const int xl2 = b.X0 + lx + 64 * h;
+                const int gxh = b.ox + xl2;
+                hy_vol[j][h] = hy_use[j] && gyh >= 0 && gyh < G.ny && gxh < G.nx;
+                hy_box[j][h] = hy_use[j] && ybl >= 0 && ybl < b.sy && xl2 < b.sx;
+                hy_colv[j][h] = rv + uint32_t(min(gxh, G.nx - 1));
+                hy_colb[j][h] = rb + uint32_t(min(xl2, b.sx - 1));
             }
-            hy_row_lds[j] = sy ? BY + 1 : 0;
+            hy_row_lds[j] = sy ? TR + 1 : 0;
         }
     }
 };
@@ -309,28 +323,27 @@ __device__ __forceinline__ int box_labels(const RhsState* __restrict__ st, int s
 // The five edge weights of a voxel in plane k, column v of the LDS tile
 // (-x, +x, -y, +y from LDS, +z from the registers), zero across the volume
 // border; d adds the -z weight carried from the previous plane.
-template <typename T, int BY, int U, int VX>
+template <typename T, typename Lanes, int U>
 struct Stencil {
+    using Tile = T[U][Lanes::TR + 2][Lanes::TC + 2];
     T wxm, wxp, wym, wyp, wzp, d;
-    __device__ __forceinline__ void eval(const T (&sg)[U][BY + 2][64 * VX + 2], int k, int v,
-                                         const TileLanes<BY, U, VX>& L, const Geom& G, int gz,
-                                         T gc, T gzn, T wzm, const WCoef& wc) {
-        const int c = 64 * v + L.lx;
-        wxm = L.gx[v] > 0 ? Weight<T>::of(gc - sg[k][L.ly + 1][c], wc) : T(0);
-        wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][L.ly + 1][c + 2], wc) : T(0);
-        wym = L.gy > 0 ? Weight<T>::of(gc - sg[k][L.ly][c + 1], wc) : T(0);
-        wyp = L.gy + 1 < G.ny ? Weight<T>::of(gc - sg[k][L.ly + 2][c + 1], wc) : T(0);
+    __device__ __forceinline__ void eval(const Tile& sg, int k, int v, const Lanes& L,
+                                         const Geom& G, int gz, T gc, T gzn, T wzm,
+                                         const WCoef& wc) {
+        const int r = L.lr[v], c = L.lc[v];
+        wxm = L.gx[v] > 0 ? Weight<T>::of(gc - sg[k][r][c - 1], wc) : T(0);
+        wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][r][c + 1], wc) : T(0);
+        wym = L.gy[v] > 0 ? Weight<T>::of(gc - sg[k][r - 1][c], wc) : T(0);
+        wyp = L.gy[v] + 1 < G.ny ? Weight<T>::of(gc - sg[k][r + 1][c], wc) : T(0);
         wzp = gz + 1 < G.nz ? Weight<T>::of(gc - gzn, wc) : T(0);
         d = wxm + wxp + wym + wyp + wzm + wzp;
     }
     // q = d p - sum_j w_j p_j
-    __device__ __forceinline__ T apply(const T (&sp)[U][BY + 2][64 * VX + 2], int k, int v,
-                                       const TileLanes<BY, U, VX>& L, T wzm, T pc, T pzm,
-                                       T pzp) const {
-        const int c = 64 * v + L.lx;
-        return d * pc - (wxm * sp[k][L.ly + 1][c] + wxp * sp[k][L.ly + 1][c + 2] +
-                         wym * sp[k][L.ly][c + 1] + wyp * sp[k][L.ly + 2][c + 1] + wzm * pzm +
-                         wzp * pzp);
+    __device__ __forceinline__ T apply(const Tile& sp, int k, int v, const Lanes& L, T wzm, T pc,
+                                       T pzm, T pzp) const {
+        const int r = L.lr[v], c = L.lc[v];
+        return d * pc - (wxm * sp[k][r][c - 1] + wxp * sp[k][r][c + 1] + wym * sp[k][r - 1][c] +
+                         wyp * sp[k][r + 1][c] + wzm * pzm + wzp * pzp);
     }
 };
 
@@ -338,16 +351,16 @@ struct Stencil {
 // neighbours; zero on seeds and outside the box), q = A p_new, partial
 // p_new.q per label.  Label r reads p_old from buffer st.pcur of pb0/pb1 and
 // writes p_new to the other one.  qout (optional) receives q.
-template <typename V, typename T, int R, int BY, int U, int VX, typename TS>
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
     const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
     const RhsState* __restrict__ st, double* __restrict__ part) {
-    using Lanes = TileLanes<BY, U, VX>;
+    using Lanes = TileLanes<BY, U, VX, YM>;
     constexpr int NYH = Lanes::NYH;
-    constexpr int TW = Lanes::TW;
-    __shared__ T sg[U][BY + 2][TW + 2];
-    __shared__ T sp[R][U][BY + 2][TW + 2];
+    constexpr int HV = Lanes::HV;
+    __shared__ T sg[U][Lanes::TR + 2][Lanes::TC + 2];
+    __shared__ T sp[R][U][Lanes::TR + 2][Lanes::TC + 2];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -425,17 +438,17 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                     hxo[r] = ldu(po[r] + o.b, L.hx_colb);
                 }
             }
-            T hyg[NYH][VX], hyz[NYH][R][VX], hyo[NYH][R][VX];
+            T hyg[NYH][HV], hyz[NYH][R][HV], hyo[NYH][R][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
 #pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    hyg[j][v] = (T)ldu(vol + o.v, L.hy_colv[j][v]);
+                for (int h = 0; h < HV; ++h) {
+                    hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        hyz[j][r][v] = ldu(zr[r] + o.b, L.hy_colb[j][v]);
-                        hyo[j][r][v] = ldu(po[r] + o.b, L.hy_colb[j][v]);
+                        hyz[j][r][h] = ldu(zr[r] + o.b, L.hy_colb[j][h]);
+                        hyo[j][r][h] = ldu(po[r] + o.b, L.hy_colb[j][h]);
                     }
                 }
             }
@@ -452,31 +465,30 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                             Pv[k + 1][r][v] =
                                 nin[k - 1] ? zN[k - 1][r][v] + bet[r] * oN[k - 1][r][v] : T(0);
                     }
-                    const int c = 64 * v + L.lx + 1;
-                    sg[k][L.ly + 1][c] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
+                    sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        sp[r][k][L.ly + 1][c] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
+                        sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
                 }
             }
             if (L.hx_use) {
-                sg[L.hx_k][L.ly + 1][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
+                sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    sp[r][L.hx_k][L.ly + 1][L.hx_col_lds] =
+                    sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] =
                         L.hx_box ? hxz[r] + bet[r] * hxo[r] : T(0);
             }
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 if (L.hy_use[j]) {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        const int c = 64 * v + L.lx + 1;
-                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][v] ? hyg[j][v] : T(0);
+                    for (int h = 0; h < HV; ++h) {
+                        const int c = 64 * h + L.lx + 1;
+                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
 #pragma unroll
                         for (int r = 0; r < R; ++r)
                             sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
-                                L.hy_box[j][v] ? hyz[j][r][v] + bet[r] * hyo[j][r][v] : T(0);
+                                L.hy_box[j][h] ? hyz[j][r][h] + bet[r] * hyo[j][r][h] : T(0);
                     }
                 }
             }
@@ -498,7 +510,7 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                 for (int r = 0; r < R; ++r) prow[r] = pw[r] + (int64_t)lz * bplane;
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Stencil<T, BY, U, VX> S;
+                    Stencil<T, Lanes, U> S;
                     S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
                     const bool valid = L.in_box[v] && zin;
 #pragma unroll
@@ -533,16 +545,16 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 // Pass 2: q = A p (p = buffer st.pcur, just written by pass 1); on unknowns
 // x += alpha p, r = d z - alpha q, z = r / d; partials r.z and r.r per label
 // ([2R][ntiles]).
-template <typename V, typename T, int R, int BY, int U, int VX, typename TS>
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
     const T* __restrict__ pb1, const RhsState* __restrict__ st, double* __restrict__ part) {
-    using Lanes = TileLanes<BY, U, VX>;
+    using Lanes = TileLanes<BY, U, VX, YM>;
     constexpr int NYH = Lanes::NYH;
-    constexpr int TW = Lanes::TW;
-    __shared__ T sg[U][BY + 2][TW + 2];
-    __shared__ T sp[R][U][BY + 2][TW + 2];
+    constexpr int HV = Lanes::HV;
+    __shared__ T sg[U][Lanes::TR + 2][Lanes::TC + 2];
+    __shared__ T sp[R][U][Lanes::TR + 2][Lanes::TC + 2];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -622,15 +634,15 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
 #pragma unroll
                 for (int r = 0; r < R; ++r) hxp[r] = ldu(pr[r] + o.b, L.hx_colb);
             }
-            T hyg[NYH][VX], hyp[NYH][R][VX];
+            T hyg[NYH][HV], hyp[NYH][R][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
 #pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    hyg[j][v] = (T)ldu(vol + o.v, L.hy_colv[j][v]);
+                for (int h = 0; h < HV; ++h) {
+                    hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) hyp[j][r][v] = ldu(pr[r] + o.b, L.hy_colb[j][v]);
+                    for (int r = 0; r < R; ++r) hyp[j][r][h] = ldu(pr[r] + o.b, L.hy_colb[j][h]);
                 }
             }
             __syncthreads();
@@ -638,29 +650,28 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
             for (int k = 0; k < U; ++k)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    const int c = 64 * v + L.lx + 1;
-                    sg[k][L.ly + 1][c] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
+                    sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        sp[r][k][L.ly + 1][c] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
+                        sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
                 }
             if (L.hx_use) {
-                sg[L.hx_k][L.ly + 1][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
+                sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    sp[r][L.hx_k][L.ly + 1][L.hx_col_lds] = L.hx_box ? hxp[r] : T(0);
+                    sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_box ? hxp[r] : T(0);
             }
 #pragma unroll
             for (int j = 0; j < NYH; ++j) {
                 if (L.hy_use[j]) {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        const int c = 64 * v + L.lx + 1;
-                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][v] ? hyg[j][v] : T(0);
+                    for (int h = 0; h < HV; ++h) {
+                        const int c = 64 * h + L.lx + 1;
+                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
 #pragma unroll
                         for (int r = 0; r < R; ++r)
                             sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
-                                L.hy_box[j][v] ? hyp[j][r][v] : T(0);
+                                L.hy_box[j][h] ? hyp[j][r][h] : T(0);
                     }
                 }
             }
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
                 const int64_t ob = (int64_t)lz * bt.sx * bt.sy;
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Stencil<T, BY, U, VX> S;
+                    Stencil<T, Lanes, U> S;
                     S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
                     const T dinv = T(1) / S.d;
                     const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
@@ -753,19 +764,20 @@ struct XCell {
 // refreshes z of the labels flagged for it (st.outer_active == 2).
 // Tiled like the passes (one plane per batch): every cell's x~ is formed once
 // by the lane that loads it and shared through LDS.
-template <typename V, typename T, int R, int BY, int VX, typename TS>
+template <typename V, typename T, int R, int BY, int VX, typename TS, bool YM = false>
 __global__ __launch_bounds__(64 * BY) void k_residual(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     Shell sh, int lab0, const double* __restrict__ x64, const double* __restrict__ rhs,
     T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
     const RhsState* __restrict__ st, double* __restrict__ part) {
     constexpr int NQ = 4 * R + 2;
-    using Lanes = TileLanes<BY, 1, VX>;
+    using Lanes = TileLanes<BY, 1, VX, YM>;
     constexpr int NYH = Lanes::NYH;
-    constexpr int TW = Lanes::TW;
-    __shared__ double sg[BY + 2][TW + 2];
-    __shared__ double sx[R][BY + 2][TW + 2];
-    __shared__ uint8_t sdir[BY + 2][TW + 2];
+    constexpr int HV = Lanes::HV;
+    constexpr int LR = Lanes::TR + 2, LC = Lanes::TC + 2;
+    __shared__ double sg[LR][LC];
+    __shared__ double sx[R][LR][LC];
+    __shared__ uint8_t sdir[LR][LC];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -801,7 +813,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 for (int r = 0; r < R; ++r)
                     xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.colb[v]) : 0.0;
                 c[v].make(gv, lb[v], xb, L.in_vol[v] && zvol, L.in_box[v] && o.inb, sh, lab0,
-                          bt.gox + L.gx[v], bt.goy + L.gy, bt.goz + gz);
+                          bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz);
             }
         };
 
@@ -824,49 +836,48 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 for (int r = 0; r < R; ++r)
                     xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hx_colb) : 0.0;
                 hx.make(gv, lb, xb, L.hx_vol && zvol, L.hx_box && o.inb, sh, lab0,
-                        bt.gox + L.hx_gx, bt.goy + L.gy, bt.goz + gz);
+                        bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz);
             }
-            XCell<R> hy[NYH][VX];
+            XCell<R> hy[NYH][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j)
 #pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    const double gv = (double)ldu(vol + o.v, L.hy_colv[j][v]);
-                    const uint8_t lb = ldu(lab + o.v, L.hy_colv[j][v]);
+                for (int h = 0; h < HV; ++h) {
+                    const double gv = (double)ldu(vol + o.v, L.hy_colv[j][h]);
+                    const uint8_t lb = ldu(lab + o.v, L.hy_colv[j][h]);
                     double xb[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hy_colb[j][v])
+                        xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hy_colb[j][h])
                                     : 0.0;
-                    hy[j][v].make(gv, lb, xb, L.hy_vol[j][v] && zvol, L.hy_box[j][v] && o.inb,
-                                  sh, lab0, bt.gox + L.gx[v], bt.goy + L.hy_gy[j],
-                                  bt.goz + gz);
+                    hy[j][h].make(gv, lb, xb, L.hy_vol[j][h] && zvol, L.hy_box[j][h] && o.inb,
+                                  sh, lab0, bt.gox + L.gx[0] + 64 * h,
+                                  bt.goy + L.hy_gy[j], bt.goz + gz);
                 }
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                const int c = 64 * v + L.lx + 1;
-                sg[L.ly + 1][c] = cc[v].g;
-                sdir[L.ly + 1][c] = cc[v].dir;
+                sg[L.lr[v]][L.lc[v]] = cc[v].g;
+                sdir[L.lr[v]][L.lc[v]] = cc[v].dir;
 #pragma unroll
-                for (int r = 0; r < R; ++r) sx[r][L.ly + 1][c] = cc[v].xt[r];
+                for (int r = 0; r < R; ++r) sx[r][L.lr[v]][L.lc[v]] = cc[v].xt[r];
             }
             if (L.hx_use) {
-                sg[L.ly + 1][L.hx_col_lds] = hx.g;
-                sdir[L.ly + 1][L.hx_col_lds] = hx.dir;
+                sg[L.hx_row_lds][L.hx_col_lds] = hx.g;
+                sdir[L.hx_row_lds][L.hx_col_lds] = hx.dir;
 #pragma unroll
-                for (int r = 0; r < R; ++r) sx[r][L.ly + 1][L.hx_col_lds] = hx.xt[r];
+                for (int r = 0; r < R; ++r) sx[r][L.hx_row_lds][L.hx_col_lds] = hx.xt[r];
             }
 #pragma unroll
             for (int j = 0; j < NYH; ++j)
                 if (L.hy_use[j]) {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        const int c = 64 * v + L.lx + 1;
-                        sg[L.hy_row_lds[j]][c] = hy[j][v].g;
-                        sdir[L.hy_row_lds[j]][c] = hy[j][v].dir;
+                    for (int h = 0; h < HV; ++h) {
+                        const int c = 64 * h + L.lx + 1;
+                        sg[L.hy_row_lds[j]][c] = hy[j][h].g;
+                        sdir[L.hy_row_lds[j]][c] = hy[j][h].dir;
 #pragma unroll
-                        for (int r = 0; r < R; ++r) sx[r][L.hy_row_lds[j]][c] = hy[j][v].xt[r];
+                        for (int r = 0; r < R; ++r) sx[r][L.hy_row_lds[j]][c] = hy[j][h].xt[r];
                     }
                 }
             __syncthreads();
@@ -889,12 +900,12 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                     }
                     continue;
                 }
-                const int c = 64 * v + L.lx;
+                const int c = L.lc[v], rr = L.lr[v];
                 // neighbour order -x, +x, -y, +y, -z, +z (the passes sum d in this order)
-                const bool hv[6] = {L.gx[v] > 0, L.gx[v] + 1 < G.nx, L.gy > 0, L.gy + 1 < G.ny,
-                                    gz > 0, gz + 1 < G.nz};
-                const int ry[6] = {L.ly + 1, L.ly + 1, L.ly, L.ly + 2, 0, 0};
-                const int rx[6] = {c, c + 2, c + 1, c + 1, 0, 0};
+                const bool hv[6] = {L.gx[v] > 0, L.gx[v] + 1 < G.nx, L.gy[v] > 0,
+                                    L.gy[v] + 1 < G.ny, gz > 0, gz + 1 < G.nz};
+                const int ry[6] = {rr, rr, rr - 1, rr + 1, 0, 0};
+                const int rx[6] = {c - 1, c + 1, c, c, 0, 0};
                 double gn[6];
                 bool dn[6];
 #pragma unroll

@@ -618,9 +618,11 @@ static size_t carve_bricks(Carver& cv, const BrickPlan& P, int R, bool mixed, Br
     return cv.bytes();
 }
 
-template <typename V, typename T, int R, int BY>
+// BVX = 2: each lane owns two rows BY apart (64 x 2 BY column tiles).
+template <typename V, typename T, int R, int BY, int BVX = 1>
 struct BrickSolve {
-    static constexpr int ZU = PlaneBatch<T, 1>::value;
+    static constexpr bool YM = BVX > 1;
+    static constexpr int ZU = PlaneBatch<T, BVX>::value;
     rw_context* ctx;
     const V* vol;
     const uint8_t* lab;
@@ -645,7 +647,7 @@ struct BrickSolve {
         t.list = list;
         t.list_count = count;
         t.zc = zc;
-        t.by = BY;
+        t.by = BY * BVX;  // rows per tile
         t.xcd = xcd;
         t.ntiles = P->ntiles;
         return t;
@@ -698,13 +700,13 @@ struct BrickSolve {
         hipStream_t s = ctx->s;
         const BrickTiles ta = act();
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
-        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0,
+        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0,
                            s, vol, wc, ta, (const T*)B.z, (T*)B.p0, (T*)B.p1, (T*)nullptr, B.st,
                            B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_bfin1<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0,
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0,
                            s, vol, lab, wc, ta, mixed ? (T*)B.xi : (T*)B.x64, (T*)B.z,
                            (const T*)B.p0, (const T*)B.p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
@@ -719,7 +721,7 @@ struct BrickSolve {
         const BrickTiles tr = ref();
         hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, lab, B.st,
                            B.x64, (T*)B.xi, 0);
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, tr, sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, (T*)B.xi, 2, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_refresh<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo,
@@ -743,7 +745,7 @@ struct BrickSolve {
         // x0 = upsampled coarse solution, then the brick residuals
         hipLaunchKernelGGL((k_brick_init<T, R>), dim3(grid), dim3(256), 0, s, all(), sh, lab0, lab,
                            B.x64, mixed ? (T*)B.xi : (T*)nullptr);
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, 1, BrickTiles>), dim3(grid), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, all(), sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, mixed ? (T*)B.xi : (T*)nullptr, 1, B.st, B.part);
         hipLaunchKernelGGL((k_bfin_init<R>), dim3(nb), dim3(64), 0, s, B.part, P->ntiles, B.geo, B.st,
@@ -824,7 +826,7 @@ struct BrickSolve {
     }
 };
 
-template <typename V, typename T, int R, int BY>
+template <typename V, typename T, int R, int BY, int BVX = 1>
 static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
                             const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub,
                             int n_bricks,
@@ -833,8 +835,8 @@ static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_see
     const bool mixed = o->precision == RW_PREC_MIXED;
     const int K = seeds->num_labels;
     const int lab0 = o->solve_all_labels ? 1 : 2;
-    BrickPlan P = make_plan(bricks, n_bricks, R, BY, tc.zc, sub, fine->dims);
-    BrickSolve<V, T, R, BY> S;
+    BrickPlan P = make_plan(bricks, n_bricks, R, BY * BVX, tc.zc, sub, fine->dims);
+    BrickSolve<V, T, R, BY, BVX> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(fine->data);
     S.lab = seeds->labels;
@@ -888,7 +890,7 @@ static rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_see
         stats->refinements = int32_t(std::min<int64_t>(refreshes, INT32_MAX));
         stats->tile_by = BY;
         stats->tile_zc = tc.zc;
-        stats->tile_vx = 1;
+        stats->tile_vx = BVX;
         stats->tile_xcd = tc.brick_xcd;
     }
     if (worst < 0) set_error(std::string("brick solve failed: ") + rw_status_string((rw_status)worst));
@@ -900,6 +902,13 @@ static rw_status bricks_by(rw_context* ctx, const rw_volume* fine, const rw_seed
                            const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
                            const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
     const TileChoice tc = brick_tiles(o->precision);
+    if (tc.vx == 2) {
+        if (tc.by == 8)
+            return bricks_run<V, T, R, 8, 2>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws,
+                                             tc, st);
+        return bricks_run<V, T, R, 4, 2>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc,
+                                         st);
+    }
     if (tc.by == 8)
         return bricks_run<V, T, R, 8>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, tc, st);
     if (tc.by == 16)
@@ -1075,7 +1084,7 @@ size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32
     const int R = solve_all_labels ? num_labels : num_labels - 1;
     if (R < 1 || R > 4) return 0;
     const TileChoice tc = brick_tiles(precision);
-    BrickPlan P = make_plan(bricks, n_bricks, R, tc.by, tc.zc);
+    BrickPlan P = make_plan(bricks, n_bricks, R, tc.by * tc.vx, tc.zc);
     Carver cv(nullptr);
     return carve_bricks(cv, P, R, precision == RW_PREC_MIXED, nullptr);
 }

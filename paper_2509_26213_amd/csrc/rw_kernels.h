@@ -29,7 +29,8 @@ struct TileChoice {
     int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist
 };
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
-// Tile shape of batched brick solves (vx = 1; by in {4, 8, 16}).
+// Tile shape of batched brick solves: 64 x (by vx) column tiles, vx rows
+// per lane (1 or 2), by in {4, 8, 16}.
 TileChoice brick_tiles(int precision);
 
 // Sum NQ per-thread values over a block of NW waves in a fixed order (wave

@@ -52,13 +52,17 @@ TileChoice tuned_tiles(const Geom& G, int precision, int R) {
 TileChoice brick_tiles(int precision) {
     (void)precision;
     // measured on MI355X (4850 uneven 64^3 bricks of a 1024^3 uint16 volume,
-    // mixed): 64 x 8 column tiles of a whole brick depth beat 64 x 4 x 32 by
-    // 7 %; 64 x 16 columns lose occupancy; the XCD-aware worklist order loses
-    TileChoice c{8, 64, 0, 1};
+    // mixed): 64 x 16 column tiles of a whole brick depth, 8 waves with two
+    // rows per lane, beat 64 x 8 (one row per lane) by 4 % and 64 x 4 x 32 by
+    // 11 %; 64 x 16 with one row per lane loses occupancy; the XCD-aware
+    // worklist order loses
+    TileChoice c{8, 64, 0, 2};
     c.by = env_int("RW_BRICK_BY", c.by);
+    c.vx = env_int("RW_BRICK_VX", c.vx) == 2 ? 2 : 1;  // rows per lane
     c.zc = env_int("RW_BRICK_ZC", c.zc);
     c.brick_xcd = env_int("RW_BRICK_XCD", 0) ? 1 : 0;
     if (c.by != 4 && c.by != 8 && c.by != 16) c.by = 8;
+    if (c.vx == 2 && c.by == 16) c.by = 8;
     if (c.zc < 4) c.zc = 4;
     return c;
 }

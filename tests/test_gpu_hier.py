@@ -110,20 +110,22 @@ def test_brick_solves_match_oracle(rw, case, coarse_ref, precision):
                 assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
 
 
-@pytest.mark.parametrize("by,zc,xcd", [(4, 16, 0), (8, 64, 0), (16, 8, 1), (8, 5, 1)])
-def test_brick_tile_shapes_match_oracle(rw, case, coarse_ref, monkeypatch, by, zc, xcd):
-    """Every brick tile shape (rows per block, planes per tile, worklist
-    order) gives the oracle's brick solutions: ragged 32^3 bricks clipped by
-    the volume border, float64."""
+@pytest.mark.parametrize("by,zc,xcd,vx", [(4, 16, 0, 1), (8, 64, 0, 1), (16, 8, 1, 1),
+                                          (8, 5, 1, 1), (4, 64, 0, 2), (8, 6, 1, 2)])
+def test_brick_tile_shapes_match_oracle(rw, case, coarse_ref, monkeypatch, by, zc, xcd, vx):
+    """Every brick tile shape (waves per block, rows per lane, planes per
+    tile, worklist order) gives the oracle's brick solutions: ragged 32^3
+    bricks clipped by the volume border, float64."""
     g, _, _, coarse = coarse_ref
     monkeypatch.setenv("RW_BRICK_BY", str(by))
+    monkeypatch.setenv("RW_BRICK_VX", str(vx))
     monkeypatch.setenv("RW_BRICK_ZC", str(zc))
     monkeypatch.setenv("RW_BRICK_XCD", str(xcd))
     cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, (32, 32, 32), (5, 3, 7))
     act = [b for b, a in zip(cands, active) if a][:6]
     prob, iters, st = rw.solve_bricks(dev(case.vol), dev(case.labels), 3, case.beta, dev(coarse), 4,
                                       act, tol=1e-6, precision="fp64", return_stats=True)
-    assert st["status"] == 0 and st["tile"]["by"] == by
+    assert st["status"] == 0 and st["tile"]["by"] == by and st["tile"]["vx"] == vx
     P = host(prob)
     for (o, s), it in zip(act, iters):
         o, s = tuple(o), tuple(s)
