@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from synth import blob_case, sphere_case
-from tests._helpers import dev, host
+from tests._helpers import assert_parity, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -91,3 +91,58 @@ def test_sphere128_gradients_vs_central_differences(rw):
     rms = np.sqrt(np.mean(fds ** 2))
     err = np.abs(ads - fds) / np.maximum(np.abs(fds), rms)
     assert np.max(err) <= 1e-3, (np.max(err), fds[np.argmax(err)], ads[np.argmax(err)])
+
+
+@pytest.mark.timeout(900)
+def test_hier1024_sampled_bricks_vs_oracle(rw):
+    """The full-size hierarchical workload (1024^3 uint16, 256 blobs, 8000
+    seeds per label, K = 3, 64^3 bricks on the offset grid, the bench's tile
+    shapes): six of the GPU's active bricks (lowest and highest GPU iteration
+    counts, two clipped border bricks, two others) equal the oracle's solves
+    of those bricks, which start from the oracle's own float64 levels and its
+    own float64 coarse solution (labels 2 and 3; label 1 as their
+    complement).  Both sides stop at relative residual 1e-8, so the
+    comparison is not limited by the stopping rule."""
+    import torch
+    from oracle import c_oracle, rw_oracle as O
+    tol = 1e-8
+    c = blob_case(shape=(1024, 1024, 1024), n_blobs=256, K=3, seeds_per_label=8000, sigma=0.08,
+                  bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3, dtype="u16")
+    brick, offset = (64, 64, 64), (48, 20, 40)
+    prob, info = rw.hierarchical_solve(dev(c.vol), dev(c.labels), 3, c.beta, levels=2,
+                                       brick=brick, offset=offset, tol=tol,
+                                       coarse_precision="mixed", brick_precision="mixed",
+                                       level_dtype=torch.float32, return_info=True)
+    act = [b for b, a in zip(info["bricks"], info["active"]) if a]
+    its = [max(i) for i in info["brick_iters"]]
+    assert len(act) == len(its) > 1000
+    order = np.argsort(its)
+    clipped = [i for i, (o, s) in enumerate(act) if min(s) < 64]
+    rng = np.random.default_rng(7)
+    pick = [int(order[0]), int(order[-1]), clipped[0], clipped[-1]]
+    pick += [int(i) for i in rng.choice(len(act), 2, replace=False)]
+    gpu = {}
+    for i in pick:
+        o, s = act[i]
+        gpu[i] = host(prob[:, o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]])
+    del prob
+    torch.cuda.empty_cache()
+    # the oracle's own levels and coarse solution (float64)
+    g = O.case_g(c)
+    g2, l2 = O.downsample_mean(O.downsample_mean(g)), O.coarse_seeds(O.coarse_seeds(c.labels))
+    coarse = np.stack([c_oracle.solve_box(g2, l2, s, c.beta, tol=tol)[0] for s in (2, 3)])
+    for i in pick:
+        o, s = (tuple(v) for v in act[i])
+        lo = tuple(max(a - 1, 0) for a in o)
+        size = tuple(min(a + b + 1, n) - l for a, b, n, l in zip(o, s, c.shape, lo))
+        up = np.stack([O.upsample_trilinear(coarse[k], c.shape, 4, (lo, size)) for k in range(2)])
+
+        def shell_value(lab, zz, yy, xx, up=up, lo=lo):
+            return up[lab - 2][zz - lo[0], yy - lo[1], xx - lo[2]]
+
+        x0 = up[:, o[0] - lo[0]:o[0] - lo[0] + s[0], o[1] - lo[1]:o[1] - lo[1] + s[1],
+                o[2] - lo[2]:o[2] - lo[2] + s[2]]
+        xb, _ = O.solve_brick(g, c.labels, o, s, shell_value, x0, c.beta, tol=tol,
+                              solve_labels=[2, 3])
+        ref = np.concatenate([1.0 - xb.sum(0, keepdims=True), xb])
+        assert_parity(gpu[i], ref, what=f"brick {o} {s} ({its[i]} GPU iterations)")
