@@ -137,6 +137,47 @@ def cpu_baseline(case, gpu_iters_fp64, n_iter, threads):
                 seconds_per_solve=t_solve)
 
 
+def cpu_baseline_hier(case, coarse_iters, bricks, brick_iters, n_iter, threads, n_sample=16):
+    """The float64 C oracle on the hierarchical workload: its own level-2
+    volume (two 2x2x2 means of the float64 level 0) timed over n_iter
+    Jacobi-PCG iterations of label 2 and scaled to the GPU's coarse iteration
+    counts, plus n_sample bricks (stratified by size, clipped ones included)
+    timed over n_iter iterations each and scaled by the GPU's sum over all
+    bricks of voxels x iterations.  Returns voxels/s of the oracle."""
+    import numpy as np
+    from oracle import c_oracle, rw_oracle
+    t_all = time.perf_counter()
+    g = rw_oracle.case_g(case)
+    g2 = rw_oracle.downsample_mean(rw_oracle.downsample_mean(g))
+    l2 = rw_oracle.coarse_seeds(rw_oracle.coarse_seeds(case.labels))
+    _, it, _ = c_oracle.pcg_fixed_iters(g2, l2, 2, case.beta, n_iter, nthreads=threads)
+    setup_s, loop_s = c_oracle.last_timing()
+    t_coarse = setup_s * len(coarse_iters) + loop_s / max(it, 1) * sum(coarse_iters)
+    vox = np.array([int(np.prod(s)) for _, s in bricks])
+    order = np.argsort(vox, kind="stable")
+    pick = order[np.linspace(0, len(order) - 1, n_sample).astype(int)]
+    per_vox_iter = []
+    for i in pick:
+        o, s = bricks[i]
+        shell = np.zeros(tuple(int(v) + 2 for v in s))
+        t0 = time.perf_counter()
+        _, its, _, _ = c_oracle.solve_box(g, case.labels, 2, case.beta, tol=1e-300,
+                                          max_iter=n_iter, box=(tuple(o), tuple(s)), shell=shell,
+                                          nthreads=threads)
+        per_vox_iter.append((time.perf_counter() - t0) / (vox[i] * max(its, 1)))
+    work = sum(int(v) * sum(it) for v, it in zip(vox, brick_iters))
+    t_bricks = float(np.mean(per_vox_iter)) * work
+    n_vox = int(np.prod(case.labels.shape))
+    t_solve = t_coarse + t_bricks
+    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, kind="oracle",
+                sample=(f"level-2 {g2.shape[0]}^3 solve: {it} float64 Jacobi-PCG iterations of "
+                        f"label 2 scaled to the GPU's {sum(coarse_iters)}; {n_sample} of "
+                        f"{len(bricks)} bricks (by size) x {n_iter} iterations, scaled by the "
+                        f"GPU's sum of brick voxels x iterations ({work:.3g}); "
+                        f"{time.perf_counter() - t_all:.1f} s wall"),
+                seconds_per_solve=t_solve)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,7 +346,6 @@ def bench_hier(args):
     K, n_vox = case.K, int(np.prod(case.shape))
     vol = torch.from_numpy(case.vol).to(dev)
     lab = torch.from_numpy(case.labels).to(dev)
-    del case.vol
     brick, offset = (64, 64, 64), (48, 20, 40)
 
     def step(timing=False):
@@ -331,7 +371,7 @@ def bench_hier(args):
                                             hi=65535.0, **extra)
         torch.cuda.synchronize()
         return dict(coarse=cst, bricks=bst, n_active=len(act), n_cand=len(cands),
-                    brick_s=time.perf_counter() - t, iters=iters)
+                    brick_s=time.perf_counter() - t, iters=iters, act=act)
 
     for _ in range(args.warmup):
         step()
@@ -349,6 +389,13 @@ def bench_hier(args):
     ach1 = bytes1 / (b["pass_ms"][0] * 1e-3) / 1e9
     act_vox = b["unknowns"]
     its = np.array(o["iters"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline_hier(case, og["coarse"]["iters"], og["act"], og["iters"],
+                                    args.cpu_iters, len(os.sched_getaffinity(0)))
+        except Exception as e:  # the baseline never hides the GPU result
+            cpu = {"error": repr(e)}
     print(json.dumps({
         "metric": METRIC, "value": n_vox / sec, "unit": "voxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
@@ -374,6 +421,7 @@ def bench_hier(args):
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((b["pass_ms"][0] + b["pass_ms"][1]) * 1e-3)
         / 1e9 / HBM_PEAK_GBS,
         "coarse": {"iters": og["coarse"]["iters"], "device_ms": og["coarse"]["device_ms"]},
+        "cpu_baseline": cpu,
     }), flush=True)
 
 
