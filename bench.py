@@ -468,7 +468,7 @@ def bench_stream(args):
     t = time.perf_counter()
     _, info = streamed_solve(vol, lab, case.K, case.beta, brick=(128, 128, 128), pool=args.pool,
                              tol=1e-6, levels=2, lo=0.0, hi=65535.0, precision="mixed",
-                             labels_out=labels)
+                             labels_out=labels, update_delta=args.update_delta)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t
     seeded = lab > 0

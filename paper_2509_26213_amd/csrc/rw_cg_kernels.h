@@ -799,61 +799,76 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
-        // own column cells of one plane
-        auto own_cells = [&](int lz, XCell<R> (&c)[VX], uint8_t (&lb)[VX]) {
+        // Raw values of a cell (intensity, label, float64 iterates); loads
+        // are issued one plane (halo cells) or two planes (own cells) ahead of
+        // the plane being computed, and the cells of the embedding are formed
+        // from them one iteration later, so the loads overlap a plane's work.
+        struct Raw {
+            V g;
+            uint8_t lb;
+            double xb[R];
+        };
+        auto load_raw = [&](int64_t ov, int64_t ob, uint32_t cv, uint32_t cb, Raw& w) {
+            w.g = ldu(vol + ov, cv);
+            w.lb = ldu(lab + ov, cv);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                w.xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + ob, cb) : 0.0;
+        };
+        auto load_own = [&](int lz, Raw (&w)[VX]) {
             const PlaneOff o = plane_off(G, bt, lz);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) load_raw(o.v, o.b, L.colv[v], L.colb[v], w[v]);
+        };
+        auto load_halo = [&](int lz, Raw& wx, Raw (&wy)[NYH][HV]) {
+            const PlaneOff o = plane_off(G, bt, lz);
+            load_raw(o.v, o.b, L.hx_colv, L.hx_colb, wx);
+#pragma unroll
+            for (int j = 0; j < NYH; ++j)
+#pragma unroll
+                for (int h = 0; h < HV; ++h) load_raw(o.v, o.b, L.hy_colv[j][h], L.hy_colb[j][h], wy[j][h]);
+        };
+        auto make_own = [&](int lz, const Raw (&w)[VX], XCell<R> (&c)[VX], uint8_t (&lb)[VX]) {
             const int gz = bt.oz + lz;
             const bool zvol = gz >= 0 && gz < G.nz;
+            const bool inb = lz >= 0 && lz < bt.sz;
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                const double gv = (double)ldu(vol + o.v, L.colv[v]);
-                lb[v] = ldu(lab + o.v, L.colv[v]);
-                double xb[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.colb[v]) : 0.0;
-                c[v].make(gv, lb[v], xb, L.in_vol[v] && zvol, L.in_box[v] && o.inb, sh, lab0,
-                          bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz);
+                lb[v] = w[v].lb;
+                c[v].make((double)w[v].g, w[v].lb, w[v].xb, L.in_vol[v] && zvol, L.in_box[v] && inb,
+                          sh, lab0, bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz);
             }
         };
 
         XCell<R> cm[VX], cc[VX], cp[VX];
         uint8_t lbm[VX], lbc[VX], lbp[VX];
-        own_cells(bt.z0 - 1, cm, lbm);
-        own_cells(bt.z0, cc, lbc);
+        Raw own1[VX], own2[VX], hx0, hx1, hy0[NYH][HV], hy1[NYH][HV];
+        load_own(bt.z0 - 1, own1);
+        make_own(bt.z0 - 1, own1, cm, lbm);
+        load_own(bt.z0, own1);
+        make_own(bt.z0, own1, cc, lbc);
+        load_own(bt.z0 + 1, own1);
+        load_halo(bt.z0, hx0, hy0);
         for (int lz = bt.z0; lz < bt.z1; ++lz) {
             const int gz = bt.oz + lz;
             const bool zvol = gz >= 0 && gz < G.nz;
-            own_cells(lz + 1, cp, lbp);
-            // halo cells of plane lz
-            const PlaneOff o = plane_off(G, bt, lz);
+            const bool inb = lz >= 0 && lz < bt.sz;
+            // (A) the next loads: own cells of plane lz+2, halo cells of lz+1
+            load_own(lz + 2, own2);
+            load_halo(lz + 1, hx1, hy1);
+            // (B) cells of plane lz+1 (own) and of plane lz's halo
+            make_own(lz + 1, own1, cp, lbp);
             XCell<R> hx;
-            {
-                const double gv = (double)ldu(vol + o.v, L.hx_colv);
-                const uint8_t lb = ldu(lab + o.v, L.hx_colv);
-                double xb[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hx_colb) : 0.0;
-                hx.make(gv, lb, xb, L.hx_vol && zvol, L.hx_box && o.inb, sh, lab0,
-                        bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz);
-            }
+            hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
+                    bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz);
             XCell<R> hy[NYH][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j)
 #pragma unroll
-                for (int h = 0; h < HV; ++h) {
-                    const double gv = (double)ldu(vol + o.v, L.hy_colv[j][h]);
-                    const uint8_t lb = ldu(lab + o.v, L.hy_colv[j][h]);
-                    double xb[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + o.b, L.hy_colb[j][h])
-                                    : 0.0;
-                    hy[j][h].make(gv, lb, xb, L.hy_vol[j][h] && zvol, L.hy_box[j][h] && o.inb,
-                                  sh, lab0, bt.gox + L.gx[0] + 64 * h,
-                                  bt.goy + L.hy_gy[j], bt.goz + gz);
-                }
+                for (int h = 0; h < HV; ++h)
+                    hy[j][h].make((double)hy0[j][h].g, hy0[j][h].lb, hy0[j][h].xb,
+                                  L.hy_vol[j][h] && zvol, L.hy_box[j][h] && inb, sh, lab0,
+                                  bt.gox + L.gx[0] + 64 * h, bt.goy + L.hy_gy[j], bt.goz + gz);
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
@@ -971,13 +986,19 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                     }
                 }
             }
-            // carry planes lz, lz+1
+            // carry planes lz, lz+1 and the loads in flight
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
                 cm[v] = cc[v];
                 cc[v] = cp[v];
                 lbc[v] = lbp[v];
+                own1[v] = own2[v];
             }
+            hx0 = hx1;
+#pragma unroll
+            for (int j = 0; j < NYH; ++j)
+#pragma unroll
+                for (int h = 0; h < HV; ++h) hy0[j][h] = hy1[j][h];
         }
         block_sum_store<NQ, BY>(acc, part + bt.pidx, ts.ntiles);
     }

@@ -44,13 +44,15 @@ def _brick_grid(shape, brick):
 
 def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, tol=1e-6,
                    levels=2, lo=0.0, hi=65535.0, lo_thr=0.02, hi_thr=0.98, precision="mixed",
-                   out=None, labels_out=None, ctx=None):
+                   out=None, labels_out=None, ctx=None, update_delta=None):
     """vol_host: uint16 or float32 numpy [nz][ny][nx]; lab_host: uint8 numpy.
 
     Brick sizes must be even (level-1 blocks must not straddle bricks).
     out: float32 [K][...] host array for the probabilities; labels_out: uint8
     [...] host array for the label map.  With neither given, probabilities
-    are returned.  Returns (out, info dict with timings and counts).
+    are returned.  update_delta: the brick solves' float64 refresh threshold
+    (None: the brick default).  Returns (out, info dict with timings and
+    counts).
     """
     assert all(b % 2 == 0 for b in brick), "brick sizes must be even"
     ctx = ctx or rw.default_context()
@@ -200,7 +202,8 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
         ts = time.perf_counter()
         _, iters, bst = rw.solve_bricks(P["v"], P["l"], K, beta, coarse, f, bricks_local,
                                         prob_out=P["p"], tol=tol, precision=precision, lo=lo,
-                                        hi=hi, ctx=ctx, return_stats=True, subvols=subs)
+                                        hi=hi, ctx=ctx, return_stats=True, subvols=subs,
+                                        update_delta=update_delta)
         solve_s += time.perf_counter() - ts
         iters_all += iters
         meta.append(bst)

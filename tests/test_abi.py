@@ -59,3 +59,32 @@ def test_oracle_is_not_imported_by_the_product_path():
             if f.endswith((".py", ".hip", ".h", ".cpp", ".c")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.replace("oracle is", ""), os.path.join(dirpath, f)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (compiled by the host C compiler)."""
+    from paper_2509_26213_amd import rw
+    pairs = [("rw_dims", rw.Dims), ("rw_volume", rw.Volume), ("rw_seeds", rw.Seeds),
+             ("rw_options", rw.Options), ("rw_stats", rw.Stats), ("rw_brick", rw.Brick),
+             ("rw_subvolume", rw.SubVolume)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rw.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                               check=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
