@@ -729,17 +729,19 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
 // float64 residual: the iterate on unknowns of the box, 1 on the label's
 // seeds and 0 on other seeds (lab0 = 0: 0 on every seed), the upsampled
 // coarse value on non-seed voxels outside the box (the brick shell), 0
-// outside the volume.  dir: the cell carries Dirichlet data.
-template <int R>
+// outside the volume.  dir: the cell carries Dirichlet data.  The intensity
+// is kept in GT, the volume's own precision (float for uint16 and float32
+// volumes, which it holds exactly).
+template <typename GT, int R>
 struct XCell {
-    double g;
+    GT g;
     double xt[R];
     bool dir;
 
     __device__ __forceinline__ void make(double gv, uint8_t lb, const double (&xb)[R], bool in_vol,
                                          bool in_box, const Shell& sh, int lab0, int gx, int gy,
                                          int gz) {
-        g = in_vol ? gv : 0.0;
+        g = in_vol ? (GT)gv : GT(0);
         dir = !(in_box && lb == 0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -775,7 +777,8 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
     constexpr int NYH = Lanes::NYH;
     constexpr int HV = Lanes::HV;
     constexpr int LR = Lanes::TR + 2, LC = Lanes::TC + 2;
-    __shared__ double sg[LR][LC];
+    using GT = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
+    __shared__ GT sg[LR][LC];
     __shared__ double sx[R][LR][LC];
     __shared__ uint8_t sdir[LR][LC];
     const int cnt = ts.count();
@@ -828,7 +831,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
 #pragma unroll
                 for (int h = 0; h < HV; ++h) load_raw(o.v, o.b, L.hy_colv[j][h], L.hy_colb[j][h], wy[j][h]);
         };
-        auto make_own = [&](int lz, const Raw (&w)[VX], XCell<R> (&c)[VX], uint8_t (&lb)[VX]) {
+        auto make_own = [&](int lz, const Raw (&w)[VX], XCell<GT, R> (&c)[VX], uint8_t (&lb)[VX]) {
             const int gz = bt.oz + lz;
             const bool zvol = gz >= 0 && gz < G.nz;
             const bool inb = lz >= 0 && lz < bt.sz;
@@ -840,7 +843,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
             }
         };
 
-        XCell<R> cm[VX], cc[VX], cp[VX];
+        XCell<GT, R> cm[VX], cc[VX], cp[VX];
         uint8_t lbm[VX], lbc[VX], lbp[VX];
         Raw own1[VX], own2[VX], hx0, hx1, hy0[NYH][HV], hy1[NYH][HV];
         load_own(bt.z0 - 1, own1);
@@ -858,10 +861,10 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
             load_halo(lz + 1, hx1, hy1);
             // (B) cells of plane lz+1 (own) and of plane lz's halo
             make_own(lz + 1, own1, cp, lbp);
-            XCell<R> hx;
+            XCell<GT, R> hx;
             hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
                     bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz);
-            XCell<R> hy[NYH][HV];
+            XCell<GT, R> hy[NYH][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j)
 #pragma unroll
