@@ -72,11 +72,17 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def tile_key(tile):
+    """Canonical text of a stencil tile shape (the stats' tile dict)."""
+    return "vx={vx} by={by} zc={zc} xcd={xcd}".format(**tile)
+
+
+def measured_traffic(kernel, workload, tile):
     """Ratio of measured HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
     by a copy kernel of known size) to algorithmic bytes per launch, from the
     committed summary profiles/<kernel>_<workload>_traffic.md; None when it is
-    missing or was taken on another version of the kernel source."""
+    missing or was taken on another version of the kernel source or with
+    another tile shape than this run's."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -87,6 +93,8 @@ def measured_traffic(kernel, workload):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if vals.get("tile") != tile_key(tile):
         return None
     try:
         return float(vals["traffic_over_algorithmic"])
@@ -302,12 +310,13 @@ def main():
                    "voxels": n_vox, "labels": K, "solved_labels": s["num_solved"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass2", "achieved": ach2,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
-                     "traffic": traffic(measured_traffic("k_cg_pass2", case.name),
+                     "traffic": traffic(measured_traffic("k_cg_pass2", case.name, s["tile"]),
                                         bytes2 / max(launches2, 1)),
                      "avg_launch_us": ms2 * 1e3 / max(launches2, 1),
                      "bytes_per_launch": bytes2 / max(launches2, 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
                   "avg_launch_us": ms1 * 1e3 / max(launches1, 1)},
+        "tile": tile_key(s["tile"]),
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((ms1 + ms2) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "iters": s["iters"],
         "refinements": s["refinements"],
@@ -413,11 +422,12 @@ def bench_hier(args):
                    "refreshes": b["refinements"]},
         "roofline": {"bound": "hbm", "kernel": "k_cg_pass2 (bricks)", "achieved": ach2,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
-                     "traffic": traffic(measured_traffic("k_cg_pass2", "hier1024"),
+                     "traffic": traffic(measured_traffic("k_cg_pass2", "hier1024", b["tile"]),
                                         bytes2 / max(b["pass_launches"][1], 1)),
                      "avg_launch_us": b["pass_ms"][1] * 1e3 / max(b["pass_launches"][1], 1),
                      "bytes_per_launch": bytes2 / max(b["pass_launches"][1], 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
+        "tile": tile_key(b["tile"]),
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((b["pass_ms"][0] + b["pass_ms"][1]) * 1e-3)
         / 1e9 / HBM_PEAK_GBS,
         "coarse": {"iters": og["coarse"]["iters"], "device_ms": og["coarse"]["device_ms"]},

@@ -291,15 +291,16 @@ rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seed
                             const double* grad_x, double* grad_g_out, double* grad_beta_out,
                             void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
 
-/* Tile-shape autotuner of the whole-volume stencil kernels (64 vx x 4
- * columns, each lane owning vx columns 64 apart; zc planes; XCD-aware tile
- * order on/off): runs 2 * check_interval CG iterations of rw_solve on this
- * volume for each candidate (vx in {1, 2, 4}, 4 for mixed precision only; zc
- * in {16, 32, 64}; order in {plain, XCD-aware}) with every pass timed by events,
- * and records the fastest for later solves of the same precision, number of
- * solved labels and size class (floor(log2 voxels)) in this process.
- * prob_scratch: output buffer as for rw_solve (overwritten); ws as for
- * rw_solve; best: host, 3 ints (vx, zc, xcd) or NULL. */
+/* Tile-shape autotuner of the whole-volume stencil kernels (64 vx x by
+ * columns, each lane owning vx columns 64 apart, one row per wave; zc planes;
+ * XCD-aware tile order on/off): runs 2 * check_interval CG iterations of
+ * rw_solve on this volume for each candidate (vx in {1, 2, 4}, 4 for mixed
+ * precision only; by in {4, 8}, 8 with vx = 2 only; zc in {16, 32, 64}; order
+ * in {plain, XCD-aware}) with every pass timed by events, and records the
+ * fastest for later solves of the same precision, number of solved labels and
+ * size class (floor(log2 voxels)) in this process.  prob_scratch: output
+ * buffer as for rw_solve (overwritten); ws as for rw_solve; best: host, 4 ints
+ * (vx, zc, xcd, by) or NULL. */
 rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                       const rw_options* opts, void* prob_scratch, void* ws, size_t ws_bytes,
                       int32_t* best, void* stream);

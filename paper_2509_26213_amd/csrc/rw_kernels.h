@@ -18,12 +18,11 @@ rw_status ensure_events(rw_context* ctx, size_t n);
 rw_status ensure_host_pinned(rw_context* ctx, size_t bytes);
 rw_status ensure_dev_small(rw_context* ctx, size_t bytes);
 
-// Tile shape of the stencil kernels (64 x by columns, zc planes, XCD-aware
-// tile order on/off), from the tuning table or the environment.
-// Tile shape of the stencil kernels: 64 vx columns (each lane owns vx of
-// them, 64 apart) by `by` rows by zc planes, XCD-aware tile order or not.
-// Whole-volume solves use by = 4 and vx in {1, 2, 4}; brick solves vx = 1 and
-// by in {4, 8}.
+// Tile shape of the stencil kernels, from the tuning table or the
+// environment.  Whole volumes: 64 vx columns (each lane owns vx of them, 64
+// apart) by `by` rows by zc planes, XCD-aware tile order or not; vx in {1,
+// 2, 4}, by = 8 with vx = 2 only, else 4.  Bricks: 64 columns by `by` vx rows
+// (each lane owns vx rows, by apart), vx in {1, 2}, by in {4, 8, 16}.
 struct TileChoice {
     int by, zc, xcd, vx;
     int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist

@@ -41,6 +41,9 @@ static rw_status run_group(rw_context* ctx, const rw_volume* vol, const uint8_t*
             return run_group_vx<V, T, R, 4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
                                             r_base, worst);
     }
+    if (tc.vx == 2 && tc.by == 8)
+        return run_group_vx<V, T, R, 2, 8>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
+                                           r_base, worst);
     if (tc.vx == 2)
         return run_group_vx<V, T, R, 2>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
                                         r_base, worst);

@@ -241,15 +241,16 @@ __global__ __launch_bounds__(256) void k_finish(const uint8_t* __restrict__ lab,
 
 // ================================================================== host
 
-// Tile shape of a whole-volume solve: 64 vx x 4 columns by zc planes; vx
-// and zc come from the tuning table (rw_tune.hip); zc shrinks until the grid
-// has enough blocks.
+// Tile shape of a whole-volume solve: 64 vx x by columns (by = 8 with vx = 2
+// only, else 4) by zc planes, from the tuning table (rw_tune.hip); zc
+// shrinks until the grid has enough blocks.
 inline TileChoice choose_tiles(const Geom& G, int precision, int R) {
     TileChoice c = tuned_tiles(G, precision, R);
-    c.by = 4;
+    c.by = c.by == 8 && c.vx == 2 ? 8 : 4;
     if (c.vx != 2 && c.vx != 4) c.vx = 1;
     if (precision != RW_PREC_MIXED && c.vx > 2) c.vx = 2;
-    const int64_t cols = (int64_t)((G.nx + 64 * c.vx - 1) / (64 * c.vx)) * ((G.ny + 3) / 4);
+    const int64_t cols =
+        (int64_t)((G.nx + 64 * c.vx - 1) / (64 * c.vx)) * ((G.ny + c.by - 1) / c.by);
     while (c.zc > 4 && cols * ((G.nz + c.zc - 1) / c.zc) < 1024) c.zc = std::max(4, c.zc / 2);
     // the partial buffers are sized for 64 x 4 x 4 tiles
     c.zc = std::max(4, c.zc);
@@ -292,9 +293,9 @@ struct PlaneBatch {
     static constexpr int value = per / VX > 0 ? per / VX : 1;
 };
 
-template <typename V, typename T, int R, int VX>
+template <typename V, typename T, int R, int VX, int BY_ = 4>
 struct WholeSolve {
-    static constexpr int BY = 4;
+    static constexpr int BY = BY_;
     static constexpr int ZU = PlaneBatch<T, VX>::value;
     rw_context* ctx;
     const V* vol;
@@ -552,18 +553,18 @@ struct WholeSolve {
     }
 };
 
-template <typename V, typename T, int R, int VX>
+template <typename V, typename T, int R, int VX, int BY = 4>
 inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                               const rw_options* o, int lab0, const double* x0,
                               const GroupBuffers& B, const TileChoice& tc, void* prob_out,
                               rw_stats* stats, int r_base, int* worst) {
-    WholeSolve<V, T, R, VX> S;
+    WholeSolve<V, T, R, VX, BY> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(vol->data);
     S.lab = lab;
     S.G = make_geom(vol->dims);
     S.wc = make_wcoef(vol, o->beta, o->w_eps);
-    S.tm = make_tilemap(S.G, WholeSolve<V, T, R, VX>::BY, tc.zc, tc.xcd, VX);
+    S.tm = make_tilemap(S.G, BY, tc.zc, tc.xcd, VX);
     S.lab0 = lab0;
     S.mixed = o->precision == RW_PREC_MIXED;
     S.reliable = S.mixed && o->refine_mode == 0;

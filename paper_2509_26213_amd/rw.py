@@ -591,7 +591,7 @@ def argmax(prob, out=None, ctx=None):
 
 
 def autotune(vol, labels, K, beta, precision="mixed", lo=None, hi=None, ctx=None, **kw):
-    """Pick and record the fastest stencil tile shape for this volume; returns (vx, zc, xcd)."""
+    """Pick and record the fastest stencil tile shape for this volume; returns (vx, zc, xcd, by)."""
     import warnings
     ctx = ctx or default_context()
     V = make_volume(vol, lo, hi)
@@ -601,7 +601,7 @@ def autotune(vol, labels, K, beta, precision="mixed", lo=None, hi=None, ctx=None
     prob = torch.empty((K,) + tuple(vol.shape), dtype=dt, device=vol.device)
     nbytes = lib().rw_solve_workspace_bytes(_dims(vol.shape), K, o.precision, o.solve_all_labels)
     ws = _alloc_ws(nbytes, vol.device)
-    best = (ctypes.c_int32 * 3)()
+    best = (ctypes.c_int32 * 4)()
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         _check(lib().rw_autotune(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),

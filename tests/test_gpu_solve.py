@@ -142,22 +142,30 @@ def test_u16_volume_and_solve_all_labels(rw):
     assert np.max(np.abs(P.sum(0) - 1)) < 1e-4
 
 
-@pytest.mark.parametrize("vx,zc,xcd,shape", [(1, 4, 0, (29, 70, 131)), (2, 16, 1, (29, 70, 131)),
-                                             (4, 64, 1, (29, 70, 131)), (4, 5, 1, (29, 70, 131)),
-                                             (2, 5, 0, (29, 70, 131)), (4, 8, 0, (20, 33, 45)),
-                                             (2, 4, 1, (9, 5, 300))])
-def test_tile_shapes_agree(rw, monkeypatch, vx, zc, xcd, shape):
-    """Every tile shape (columns per lane, planes per tile, tile order; tiles
-    wider than the volume and ragged in x, y and z) gives the oracle's
-    solution; float64 solves take vx = 4 as 2.  The 9 x 5 x 300 rod is badly
-    conditioned: stopped at relative residual 1e-6 the oracle itself is 4e-3
-    from its own tol-1e-12 solution, so both sides solve to tight tolerances
-    (oracle 1e-11, float64 1e-10, mixed 1e-9)."""
+@pytest.mark.parametrize("vx,by,zc,xcd,shape", [(1, 4, 4, 0, (29, 70, 131)),
+                                                (2, 4, 16, 1, (29, 70, 131)),
+                                                (4, 4, 64, 1, (29, 70, 131)),
+                                                (4, 4, 5, 1, (29, 70, 131)),
+                                                (2, 4, 5, 0, (29, 70, 131)),
+                                                (4, 4, 8, 0, (20, 33, 45)),
+                                                (2, 4, 4, 1, (9, 5, 300)),
+                                                (2, 8, 64, 0, (29, 70, 131)),
+                                                (2, 8, 5, 1, (29, 70, 131)),
+                                                (2, 8, 16, 0, (20, 33, 45)),
+                                                (2, 8, 4, 1, (9, 5, 300))])
+def test_tile_shapes_agree(rw, monkeypatch, vx, by, zc, xcd, shape):
+    """Every tile shape (columns per lane, rows per tile, planes per tile,
+    tile order; tiles wider and taller than the volume and ragged in x, y and
+    z) gives the oracle's solution; float64 solves take vx = 4 as 2.  The
+    9 x 5 x 300 rod is badly conditioned: stopped at relative residual 1e-6
+    the oracle itself is 4e-3 from its own tol-1e-12 solution, so both sides
+    solve to tight tolerances (oracle 1e-11, float64 1e-10, mixed 1e-9)."""
     c = blob_case(shape=shape, n_blobs=5, K=3, seeds_per_label=30, sigma=0.08,
                   rmin=4, rmax=12, seed=13)
     ref, _ = _oracle_same(c, tol=1e-11)
     vol, lab = _case_tensors(c)
     monkeypatch.setenv("RW_TILE_VX", str(vx))
+    monkeypatch.setenv("RW_TILE_BY", str(by))
     monkeypatch.setenv("RW_TILE_ZC", str(zc))
     monkeypatch.setenv("RW_TILE_XCD", str(xcd))
     for precision, tol in (("fp64", 1e-10), ("mixed", 1e-9)):
@@ -165,8 +173,9 @@ def test_tile_shapes_agree(rw, monkeypatch, vx, zc, xcd, shape):
                                return_stats=True)
         assert st["status"] == 0
         assert st["tile"]["vx"] == (min(vx, 2) if precision == "fp64" else vx)
+        assert st["tile"]["by"] == by
         assert st["tile"]["xcd"] == xcd
-        assert_parity(host(prob), ref, what=f"tile vx {vx} zc {zc} {precision}")
+        assert_parity(host(prob), ref, what=f"tile vx {vx} by {by} zc {zc} {precision}")
 
 
 def test_graph_and_plain_launches_bitwise_equal(rw):
@@ -295,8 +304,9 @@ def test_autotuner_records_a_tile_and_solves_agree(rw):
                   rmin=4, rmax=12, seed=17)
     vol, lab = _case_tensors(c)
     ref, _ = _oracle_same(c)
-    vx, zc, xcd = rw.autotune(vol, lab, 3, c.beta, precision="mixed")
-    assert vx in (1, 2, 4) and zc in (16, 32, 64) and xcd in (0, 1)
+    vx, zc, xcd, by = rw.autotune(vol, lab, 3, c.beta, precision="mixed")
+    assert vx in (1, 2, 4) and zc in (16, 32, 64) and xcd in (0, 1) and by in (4, 8)
+    assert by == 4 or vx == 2
     prob, _, st = rw.solve(vol, lab, 3, c.beta, precision="mixed", return_stats=True)
-    assert st["tile"]["vx"] == vx and st["tile"]["xcd"] == xcd
+    assert st["tile"]["vx"] == vx and st["tile"]["xcd"] == xcd and st["tile"]["by"] == by
     assert_parity(host(prob), ref, what="after autotune")
