@@ -63,6 +63,10 @@ typedef enum {
                           float64 residual + iterative refinement */
 } rw_precision;
 
+/* Grid size in voxels.  Supported grids: every side in [1, 2^30], a plane
+ * nx * ny of at most 2^29 voxels and at most 2^40 voxels in all; calls given
+ * larger grids return RW_ERR_INVALID_ARG before any device work, and the
+ * workspace-size functions return 0. */
 typedef struct {
     int64_t nx, ny, nz;
 } rw_dims;

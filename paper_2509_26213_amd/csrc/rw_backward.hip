@@ -151,7 +151,7 @@ using namespace rw;
 extern "C" {
 
 size_t rw_backward_workspace_bytes(rw_dims dims) {
-    if (dims.nx <= 0 || dims.ny <= 0 || dims.nz <= 0) return 0;
+    if (!dims_supported(dims)) return 0;
     Carver cv(nullptr);
     carve_group(cv, make_geom(dims), 1, false, nullptr);
     cv.take<double>(GRAD_BLOCKS + 1);

@@ -138,13 +138,21 @@ rw_status check_volume(const rw_volume* vol) {
     if (!vol->data) return invalid("volume data is NULL");
     if (vol->dims.nx <= 0 || vol->dims.ny <= 0 || vol->dims.nz <= 0)
         return invalid("volume dimensions must be positive");
-    if (vol->dims.nx > (1 << 30) || vol->dims.ny > (1 << 30) || vol->dims.nz > (1 << 30))
-        return invalid("volume dimension too large");
+    if (!dims_supported(vol->dims))
+        return invalid("volume too large (sides at most 2^30, nx * ny at most 2^29, "
+                       "nx * ny * nz at most 2^40 voxels)");
     if (vol->dtype != RW_DT_U16 && vol->dtype != RW_DT_F32 && vol->dtype != RW_DT_F64)
         return invalid("unknown volume dtype");
     if (!std::isfinite(vol->norm_lo) || !std::isfinite(vol->norm_hi))
         return (set_error("normalisation range is not finite"), RW_ERR_NONFINITE);
     return RW_OK;
+}
+
+bool dims_supported(rw_dims d) {
+    if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return false;
+    if (d.nx > (1 << 30) || d.ny > (1 << 30) || d.nz > (1 << 30)) return false;
+    const int64_t plane = d.nx * d.ny;
+    return plane <= (int64_t(1) << 29) && plane * d.nz <= (int64_t(1) << 40);
 }
 
 Geom make_geom(rw_dims d) {

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_fill(Shell sh, int K, int64_t n,
 static rw_status make_shell(const void* coarse, int32_t cdt, rw_dims cd, int32_t factor, Shell* sh) {
     if (!coarse) return invalid("coarse probabilities are NULL");
     if (cdt != RW_DT_F32 && cdt != RW_DT_F64) return invalid("coarse dtype must be F32 or F64");
-    if (cd.nx <= 0 || cd.ny <= 0 || cd.nz <= 0) return invalid("coarse dims must be positive");
+    if (!dims_supported(cd)) return invalid("coarse dims must be positive and supported");
     if (factor < 1) return invalid("factor must be >= 1");
     sh->coarse = coarse;
     sh->cdt = cdt == RW_DT_F64 ? 1 : 0;
@@ -977,7 +977,7 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
     if (!ctx || !fine_labels || !brick_size || !grid_offset || !n_candidates)
         return invalid("NULL argument");
     if (num_labels < 1 || num_labels > RW_MAX_LABELS) return invalid("num_labels must be in [1, 16]");
-    if (fine_dims.nx <= 0 || fine_dims.ny <= 0 || fine_dims.nz <= 0) return invalid("bad fine dims");
+    if (!dims_supported(fine_dims)) return invalid("fine dims must be positive and supported");
     for (int a = 0; a < 3; ++a)
         if (brick_size[a] < 1 || grid_offset[a] < 0) return invalid("bad brick size or offset");
     Shell sh;

@@ -8,6 +8,10 @@ namespace rw {
 
 rw_status invalid(const std::string& msg);
 rw_status check_volume(const rw_volume* vol);
+// Grids the kernels can address: every side in [1, 2^30], a plane of at most
+// 2^29 voxels (in-plane offsets are 32-bit byte offsets of 8-byte values)
+// and at most 2^40 voxels (tile counts are 32-bit).
+bool dims_supported(rw_dims d);
 Geom make_geom(rw_dims d);
 WCoef make_wcoef(const rw_volume* vol, double beta, double w_eps);
 rw_status stream_enter(rw_context* ctx, void* user);

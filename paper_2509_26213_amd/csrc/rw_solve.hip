@@ -180,7 +180,7 @@ extern "C" {
 
 size_t rw_solve_workspace_bytes(rw_dims dims, int32_t num_labels, int32_t precision,
                                 int32_t solve_all_labels) {
-    if (dims.nx <= 0 || dims.ny <= 0 || dims.nz <= 0 || num_labels < 1) return 0;
+    if (!dims_supported(dims) || num_labels < 1) return 0;
     const int R_total = solve_all_labels ? num_labels : num_labels - 1;
     const int Rg = std::max(1, std::min(4, R_total));
     Carver cv(nullptr);
@@ -254,7 +254,7 @@ rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
 }
 
 size_t rw_operator_workspace_bytes(rw_dims dims, int32_t precision) {
-    if (dims.nx <= 0 || dims.ny <= 0 || dims.nz <= 0) return 0;
+    if (!dims_supported(dims)) return 0;
     const Geom G = make_geom(dims);
     Carver cv(nullptr);
     cv.take<char>((precision == RW_PREC_MIXED ? 4 : 8) * size_t(G.n));

@@ -50,6 +50,14 @@ def test_host_side_validation_without_gpu():
     assert L.rw_solve_workspace_bytes(rw.Dims(0, 4, 4), 2, 0, 0) == 0
     n = L.rw_solve_workspace_bytes(rw.Dims(64, 64, 64), 2, 0, 0)
     assert n >= 64 ** 3 * 8 * 4
+    # grids the kernels cannot address are refused: a plane above 2^29 voxels
+    # (32-bit in-plane byte offsets), more than 2^40 voxels, a side above 2^30
+    assert L.rw_solve_workspace_bytes(rw.Dims(1 << 15, 1 << 14, 1), 2, 0, 0) > 0
+    assert L.rw_solve_workspace_bytes(rw.Dims(1 << 15, (1 << 14) + 1, 1), 2, 0, 0) == 0
+    assert L.rw_solve_workspace_bytes(rw.Dims(1 << 14, 1 << 14, (1 << 13) + 1), 2, 0, 0) == 0
+    assert L.rw_solve_workspace_bytes(rw.Dims((1 << 30) + 1, 1, 1), 2, 0, 0) == 0
+    assert L.rw_operator_workspace_bytes(rw.Dims(1 << 20, 1 << 10, 1), 1) == 0
+    assert L.rw_backward_workspace_bytes(rw.Dims(1 << 20, 1 << 10, 1)) == 0
 
 
 def test_oracle_is_not_imported_by_the_product_path():
