@@ -259,7 +259,8 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
  * prob_out: [K][voxels of `fine`] float32: the voxels of the bricks are
  *   overwritten (at their pool positions), other voxels untouched.
  * brick_iters: NULL or host int32 [n_bricks][R] CG iterations per brick/label.
- * ws: rw_bricks_workspace_bytes(...). */
+ * ws: rw_bricks_workspace_bytes(...), sized for every tile shape a brick
+ *   solve may use (the default and every rw_autotune_bricks candidate). */
 size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32_t num_labels,
                                  int32_t precision, int32_t solve_all_labels);
 rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* fine_seeds,
@@ -308,6 +309,24 @@ rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seed
 rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                       const rw_options* opts, void* prob_scratch, void* ws, size_t ws_bytes,
                       int32_t* best, void* stream);
+
+/* Tile-shape autotuner of the batched brick solves (tiles of 64 columns by
+ * by * rpl rows, each lane owning rpl rows by apart; zc planes; worklist in
+ * plain or XCD-aware order): runs 2 * check_interval CG iterations of
+ * rw_solve_bricks on these bricks for each candidate ((by, rpl) in {(8, 2),
+ * (4, 2), (16, 1), (8, 1), (4, 1)}, zc in {16, 32, 64}, both orders), times
+ * every pass by events, and records the shape with the least pass time per
+ * voxel-iteration for later brick solves of the same precision, number of
+ * solved labels and size class of the largest brick (floor(log2 voxels)) in
+ * this process.  Arguments as for rw_solve_bricks; prob_scratch receives
+ * partial solutions (overwritten by every candidate), ws must hold
+ * rw_bricks_workspace_bytes (which covers every candidate shape); best: host,
+ * 4 ints (by, rpl, zc, xcd order) or NULL. */
+rw_status rw_autotune_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
+                             const void* coarse_prob, int32_t coarse_dtype, rw_dims coarse_dims,
+                             int32_t factor, const rw_brick* bricks, const rw_subvolume* subvols,
+                             int32_t n_bricks, const rw_options* opts, float* prob_scratch,
+                             void* ws, size_t ws_bytes, int32_t* best, void* stream);
 
 #ifdef __cplusplus
 }

@@ -530,6 +530,13 @@ struct BrickPlan {
 };
 
 // Bricks sorted by decreasing size (stable), tiles of 64 x by x zc.
+static int64_t max_brick_voxels(const rw_brick* bricks, int n) {
+    int64_t m = 0;
+    for (int i = 0; i < n; ++i)
+        m = std::max<int64_t>(m, (int64_t)bricks[i].sx * bricks[i].sy * bricks[i].sz);
+    return m;
+}
+
 static BrickPlan make_plan(const rw_brick* bricks, int n, int R, int by, int zc,
                            const rw_subvolume* sub = nullptr, rw_dims vol = rw_dims{1, 1, 1}) {
     BrickPlan P;
@@ -901,7 +908,7 @@ template <typename V, typename T, int R>
 static rw_status bricks_by(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
                            const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
                            const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
-    const TileChoice tc = brick_tiles(o->precision);
+    const TileChoice tc = brick_tiles(o->precision, R, max_brick_voxels(bricks, n));
     if (tc.vx == 2) {
         if (tc.by == 8)
             return bricks_run<V, T, R, 8, 2>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws,
@@ -1083,10 +1090,16 @@ size_t rw_bricks_workspace_bytes(const rw_brick* bricks, int32_t n_bricks, int32
     if (n_bricks <= 0 || !bricks || num_labels < 1) return 0;
     const int R = solve_all_labels ? num_labels : num_labels - 1;
     if (R < 1 || R > 4) return 0;
-    const TileChoice tc = brick_tiles(precision);
-    BrickPlan P = make_plan(bricks, n_bricks, R, tc.by * tc.vx, tc.zc);
-    Carver cv(nullptr);
-    return carve_bricks(cv, P, R, precision == RW_PREC_MIXED, nullptr);
+    // enough for the shape in use and for every shape the autotuner may pick
+    std::vector<TileChoice> shapes = brick_candidates();
+    shapes.push_back(brick_tiles(precision, R, max_brick_voxels(bricks, n_bricks)));
+    size_t need = 0;
+    for (const TileChoice& tc : shapes) {
+        BrickPlan P = make_plan(bricks, n_bricks, R, tc.by * tc.vx, tc.zc);
+        Carver cv(nullptr);
+        need = std::max(need, carve_bricks(cv, P, R, precision == RW_PREC_MIXED, nullptr));
+    }
+    return need;
 }
 
 static rw_status check_subvolumes(const rw_brick* bricks, const rw_subvolume* sub, int n,

@@ -34,7 +34,12 @@ struct TileChoice {
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
 // Tile shape of batched brick solves: 64 x (by vx) column tiles, vx rows
 // per lane (1 or 2), by in {4, 8, 16}.
-TileChoice brick_tiles(int precision);
+// Brick tile shape for a batch whose largest brick has max_brick_vox voxels:
+// the autotuner's choice for (precision, R, floor(log2 max_brick_vox)) if it
+// ran, else the measured default with RW_BRICK_* overrides.
+TileChoice brick_tiles(int precision, int R, int64_t max_brick_vox);
+// The shapes the brick autotuner times (every one a brick solve supports).
+const std::vector<TileChoice>& brick_candidates();
 
 // Sum NQ per-thread values over a block of NW waves in a fixed order (wave
 // butterfly, then the wave totals in wave order); threads 0..NQ-1 write

@@ -60,8 +60,25 @@ TileChoice tuned_tiles(const Geom& G, int precision, int R) {
     return c;
 }
 
-TileChoice brick_tiles(int precision) {
-    (void)precision;
+namespace {
+
+std::map<std::tuple<int, int, int>, TileChoice> g_brick_tuned;  // (precision, R, size class)
+thread_local bool g_brick_forced = false;
+thread_local TileChoice g_brick_force{8, 64, 0, 2};
+
+int brick_class(int64_t max_vox) {
+    return max_vox > 0 ? int(std::floor(std::log2(double(max_vox)))) : 0;
+}
+
+}  // namespace
+
+TileChoice brick_tiles(int precision, int R, int64_t max_brick_vox) {
+    if (g_brick_forced) return g_brick_force;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_brick_tuned.find(std::make_tuple(precision, R, brick_class(max_brick_vox)));
+        if (it != g_brick_tuned.end()) return it->second;
+    }
     // measured on MI355X (4850 uneven 64^3 bricks of a 1024^3 uint16 volume,
     // mixed): 64 x 16 column tiles of a whole brick depth, 8 waves with two
     // rows per lane, beat 64 x 8 (one row per lane) by 4 % and 64 x 4 x 32 by
@@ -76,6 +93,22 @@ TileChoice brick_tiles(int precision) {
     if (c.vx == 2 && c.by == 16) c.by = 8;
     if (c.zc < 4) c.zc = 4;
     return c;
+}
+
+const std::vector<TileChoice>& brick_candidates() {
+    static const std::vector<TileChoice> cands = [] {
+        std::vector<TileChoice> v;
+        const int shapes[][2] = {{8, 2}, {4, 2}, {16, 1}, {8, 1}, {4, 1}};  // (by, rows per lane)
+        for (const auto& sh : shapes)
+            for (int zc : {16, 32, 64})
+                for (int xcd : {0, 1}) {
+                    TileChoice c{sh[0], zc, 0, sh[1]};
+                    c.brick_xcd = xcd;
+                    v.push_back(c);
+                }
+        return v;
+    }();
+    return cands;
 }
 
 }  // namespace rw
@@ -137,6 +170,54 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
         best[1] = win.zc;
         best[2] = win.xcd;
         best[3] = win.by;
+    }
+    return RW_OK;
+}
+
+rw_status rw_autotune_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
+                             const void* coarse_prob, int32_t coarse_dtype, rw_dims coarse_dims,
+                             int32_t factor, const rw_brick* bricks, const rw_subvolume* subvols,
+                             int32_t n_bricks, const rw_options* opts, float* prob_scratch,
+                             void* ws, size_t ws_bytes, int32_t* best, void* stream) {
+    if (!ctx || !seeds || !opts || !prob_scratch) return invalid("NULL argument");
+    if (n_bricks <= 0 || !bricks) return invalid("no bricks to tune on");
+    const int K = seeds->num_labels;
+    const int R = std::max(1, std::min(4, opts->solve_all_labels ? K : K - 1));
+    int64_t max_vox = 0;
+    for (int i = 0; i < n_bricks; ++i)
+        max_vox = std::max<int64_t>(max_vox, (int64_t)bricks[i].sx * bricks[i].sy * bricks[i].sz);
+    rw_options o = *opts;
+    o.kernel_timing = 1;
+    o.max_iter = std::max(2, o.check_interval) * 2;
+    double best_t = INFINITY;
+    TileChoice win = brick_tiles(opts->precision, R, max_vox);
+    for (const TileChoice& cand : brick_candidates()) {
+        g_brick_forced = true;
+        g_brick_force = cand;
+        rw_stats st;
+        memset(&st, 0, sizeof(st));
+        // every candidate writes the scratch output
+        rw_status e = rw_solve_bricks(ctx, fine, seeds, coarse_prob, coarse_dtype, coarse_dims,
+                                      factor, bricks, subvols, n_bricks, &o, prob_scratch, nullptr,
+                                      ws, ws_bytes, &st, stream);
+        g_brick_forced = false;
+        if (e < 0) return e;
+        if (st.rhs_voxel_iterations <= 0) continue;
+        const double t = (st.pass_ms[0] + st.pass_ms[1]) / double(st.rhs_voxel_iterations);
+        if (t < best_t) {
+            best_t = t;
+            win = cand;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_brick_tuned[std::make_tuple(opts->precision, R, brick_class(max_vox))] = win;
+    }
+    if (best) {
+        best[0] = win.by;
+        best[1] = win.vx;
+        best[2] = win.zc;
+        best[3] = win.brick_xcd;
     }
     return RW_OK;
 }

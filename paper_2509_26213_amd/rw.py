@@ -37,7 +37,8 @@ EXPORTS = [
     "rw_default_options", "rw_minmax", "rw_build_weights", "rw_operator_workspace_bytes",
     "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
-    "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_argmax",
+    "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_autotune_bricks",
+    "rw_argmax",
 ]
 
 
@@ -159,6 +160,10 @@ def lib():
     L.rw_argmax.argtypes = [P, P, I32, I32, ctypes.c_int64, P, P]
     L.rw_autotune.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                               ctypes.POINTER(Options), P, P, SZ, ctypes.POINTER(I32), P]
+    L.rw_autotune_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, I32,
+                                     Dims, I32, ctypes.POINTER(Brick), ctypes.POINTER(SubVolume),
+                                     I32, ctypes.POINTER(Options), P, P, SZ, ctypes.POINTER(I32),
+                                     P]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is ctypes.c_int:
@@ -475,6 +480,34 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
         d["status"] = status
         return prob_out, it, d
     return prob_out, it
+
+
+def autotune_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, tol=1e-6,
+                    precision="mixed", lo=None, hi=None, ctx=None, subvols=None, **kw):
+    """Pick and record the fastest brick tile shape for batches like this one;
+    returns (by, rows per lane, zc, xcd order).  Arguments as for solve_bricks."""
+    import warnings
+    ctx = ctx or default_context()
+    if kw.get("update_delta") is None:
+        kw["update_delta"] = BRICK_UPDATE_DELTA
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, K)
+    o = options(beta, tol, precision, **kw)
+    scratch = torch.zeros((K,) + tuple(vol.shape), dtype=torch.float32, device=vol.device)
+    arr = _bricks_array(bricks)
+    n = len(bricks)
+    nbytes = lib().rw_bricks_workspace_bytes(arr, n, K, o.precision, o.solve_all_labels)
+    ws = _alloc_ws(nbytes, vol.device)
+    sv = _subvols_array(subvols, n)
+    best = (ctypes.c_int32 * 4)()
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        _check(lib().rw_autotune_bricks(ctx.handle, ctypes.byref(V), ctypes.byref(S),
+                                        _ptr(coarse_prob), _dt_code(coarse_prob),
+                                        _dims(coarse_prob.shape[1:]), int(factor), arr, sv, n,
+                                        ctypes.byref(o), _ptr(scratch), _ptr(ws), nbytes, best,
+                                        _stream()), "rw_autotune_bricks")
+    return tuple(best)
 
 
 def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offset=(0, 0, 0),

@@ -195,3 +195,34 @@ def test_hierarchical_pipeline_matches_oracle(rw, case, brick_precision):
         sl = tuple(slice(x, x + y) for x, y in zip(o, s))
         assert_parity(P[:, sl[0], sl[1], sl[2]], ref["prob"][:, sl[0], sl[1], sl[2]],
                       what=f"brick {o}")
+
+
+def test_brick_autotuner_records_a_tile_and_solves_agree(rw, case, coarse_ref):
+    """rw_autotune_bricks times every candidate brick tile shape on a batch and
+    records the fastest; later mixed brick solves with the same label count
+    and brick size class use it and still give the oracle's brick solutions
+    (ragged 32^3 bricks clipped by the volume border)."""
+    g, _, _, coarse = coarse_ref
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, (32, 32, 32), (5, 3, 7))
+    act = [b for b, a in zip(cands, active) if a][:6]
+    vol, lab, cp = dev(case.vol), dev(case.labels), dev(coarse)
+    by, rpl, zc, xcd = rw.autotune_bricks(vol, lab, 3, case.beta, cp, 4, act, precision="mixed")
+    assert (by, rpl) in {(8, 2), (4, 2), (16, 1), (8, 1), (4, 1)}
+    assert zc in (16, 32, 64) and xcd in (0, 1)
+    prob, iters, st = rw.solve_bricks(vol, lab, 3, case.beta, cp, 4, act, tol=1e-6,
+                                      precision="mixed", return_stats=True)
+    assert st["status"] == 0
+    t = st["tile"]
+    assert (t["by"], t["vx"], t["zc"], t["xcd"]) == (by, rpl, zc, xcd)
+    P = host(prob)
+    for o, s in act:
+        o, s = tuple(o), tuple(s)
+        Pf = _up(coarse, case.shape, 4, tuple(np.array(o) - 1), tuple(np.array(s) + 2))
+
+        def shell_value(lab_, zz, yy, xx, Pf=Pf, o=o):
+            return Pf[lab_ - 1][zz - o[0] + 1, yy - o[1] + 1, xx - o[2] + 1]
+
+        xb, _ = O.solve_brick(g, case.labels, o, s, shell_value, Pf[:, 1:-1, 1:-1, 1:-1],
+                              case.beta, tol=1e-6)
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        assert_parity(P[:, sl[0], sl[1], sl[2]], xb, what=f"brick {o} after autotune")
