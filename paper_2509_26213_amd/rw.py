@@ -510,13 +510,27 @@ def autotune_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, tol=1e-6,
     return tuple(best)
 
 
+def _touches(o, s, roi):
+    """Whether the brick (origin o, size s; z, y, x) meets the box roi
+    ((z0, z1), (y0, y1), (x0, x1)), half-open."""
+    return all(a < hi_ and a + b > lo_ for a, b, (lo_, hi_) in zip(o, s, roi))
+
+
 def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offset=(0, 0, 0),
                        tol=1e-6, coarse_precision="fp64", brick_precision="mixed", lo=None,
                        hi=None, lo_thr=0.02, hi_thr=0.98, ctx=None, return_info=False,
-                       level_dtype=torch.float64):
+                       level_dtype=torch.float64, roi=None):
     """Coarse-to-fine random walker: LOD levels, whole coarse solve, brick
     classification, batched solve of the uncertain bricks, upsampled fill of
-    the others.  Every step runs in the library; this only sequences calls."""
+    the others.  Every step runs in the library; this only sequences calls.
+
+    roi: None (the whole volume) or ((z0, z1), (y0, y1), (x0, x1)), a
+    half-open voxel box: lazy evaluation of a requested region (Sec. IV-B's
+    evaluation of only what a view needs).  The coarse level is still solved
+    whole (it gives every brick its Dirichlet data), but only the bricks that
+    meet the box are solved or filled; each brick's solution does not depend
+    on which other bricks share its batch, so the box holds exactly what the
+    full solve gives there.  Voxels of bricks outside the box are 0."""
     ctx = ctx or default_context()
     V = make_volume(vol, lo, hi)
     g, lab = vol, labels
@@ -528,9 +542,11 @@ def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offse
                            argmax=False, ctx=ctx, return_stats=True)
     f = 2 ** levels
     cands, active = classify_bricks(coarse, labels, f, brick, offset, lo_thr, hi_thr, ctx=ctx)
-    act = [b for b, a in zip(cands, active) if a]
-    ina = [b for b, a in zip(cands, active) if not a]
-    prob = torch.empty((K,) + tuple(vol.shape), dtype=torch.float32, device=vol.device)
+    want = [roi is None or _touches(o, s, roi) for o, s in cands]
+    act = [b for b, a, w in zip(cands, active, want) if a and w]
+    ina = [b for b, a, w in zip(cands, active, want) if not a and w]
+    alloc = torch.empty if roi is None else torch.zeros
+    prob = alloc((K,) + tuple(vol.shape), dtype=torch.float32, device=vol.device)
     if ina:
         fill_bricks(coarse, labels, f, ina, prob, ctx=ctx)
     bst = None
@@ -541,7 +557,7 @@ def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offse
                                      ctx=ctx, return_stats=True)
     if return_info:
         return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
-                          brick_iters=iters, brick_stats=bst)
+                          evaluated=want, brick_iters=iters, brick_stats=bst)
     return prob
 
 

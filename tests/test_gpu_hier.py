@@ -226,3 +226,29 @@ def test_brick_autotuner_records_a_tile_and_solves_agree(rw, case, coarse_ref):
                               case.beta, tol=1e-6)
         sl = tuple(slice(a, a + b) for a, b in zip(o, s))
         assert_parity(P[:, sl[0], sl[1], sl[2]], xb, what=f"brick {o} after autotune")
+
+
+@pytest.mark.parametrize("roi", [((0, 20), (10, 30), (30, 70)), ((40, 45), (0, 52), (0, 9))])
+def test_region_of_interest_equals_full_solve(rw, case, roi):
+    """Lazy evaluation of a region: only the bricks meeting the box are solved
+    or filled, and inside the box the result equals the full hierarchical
+    solve bit for bit (a brick's solve does not depend on its batch)."""
+    import torch
+    brick, offset = (16, 16, 16), (5, 3, 7)
+    vol, lab = dev(case.vol), dev(case.labels)
+    full, finfo = rw.hierarchical_solve(vol, lab, 3, case.beta, levels=2, brick=brick,
+                                        offset=offset, brick_precision="mixed",
+                                        return_info=True)
+    part, pinfo = rw.hierarchical_solve(vol, lab, 3, case.beta, levels=2, brick=brick,
+                                        offset=offset, brick_precision="mixed", roi=roi,
+                                        return_info=True)
+    assert torch.equal(finfo["coarse"], pinfo["coarse"])
+    n_eval = sum(pinfo["evaluated"])
+    assert 0 < n_eval < len(pinfo["bricks"])
+    sl = tuple(slice(a, b) for a, b in roi)
+    assert torch.equal(part[:, sl[0], sl[1], sl[2]], full[:, sl[0], sl[1], sl[2]])
+    # every voxel of an unevaluated brick is left 0
+    for (o, s), e in zip(pinfo["bricks"], pinfo["evaluated"]):
+        if not e:
+            bs = tuple(slice(a, a + b) for a, b in zip(o, s))
+            assert not bool(part[:, bs[0], bs[1], bs[2]].any())
