@@ -105,8 +105,10 @@ typedef struct {
     int32_t refine_mode;      /* mixed: 0 = one CG run whose residual is
                                  recomputed in float64 as it falls (reliable
                                  updates), 1 = restarted iterative refinement */
-    const void* x0;       /* device, initial guess [R][nz][ny][nx] float64 for the
-                             solved labels (read on unseeded voxels), or NULL = 0 */
+    const void* x0;       /* device, initial guess or NULL.  rw_solve: [R][nz][ny][nx]
+                             float64 for the solved labels (NULL = 0); rw_solve_bricks:
+                             [K][fine voxels] float32 as prob_out (NULL = upsampled
+                             coarse).  Read on unseeded voxels. */
 } rw_options;
 
 /* Statistics of one call (host memory). */
@@ -247,10 +249,14 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
  * Each brick solves the random walker restricted to it: unknowns are its
  * unseeded voxels; Dirichlet data are its seeds and every in-volume face
  * neighbour outside it (seed value if seeded, else the upsampled coarse
- * probability).  x0 = the upsampled coarse probabilities; stopping
- * ||r|| <= tol ||b|| per brick and label (b of the brick system).
- * Precision MIXED (float32 CG, float64 dots, float64 residual refreshes) or
- * FP64; opts->x0 is ignored.  Bricks must lie inside their volume.
+ * probability).  Initial guess: opts->x0 = NULL gives the upsampled coarse
+ * probabilities; otherwise opts->x0 is a device float32 [K][voxels of `fine`]
+ * array in the layout of prob_out (a previous result may be passed back, as
+ * for a warm-started re-solve after a seed edit), read on the bricks'
+ * unseeded voxels for the solved labels.  Stopping ||r|| <= tol ||b|| per
+ * brick and label (b of the brick system).  Precision MIXED (float32 CG,
+ * float64 dots, float64 residual refreshes) or FP64.  Bricks must lie inside
+ * their volume.
  * bricks: host array of n_bricks.
  * subvols: NULL (every brick lies in `fine`), or host array of n_bricks: brick
  *   i lies in sub-volume i of the pool `fine` (its data and labels, with

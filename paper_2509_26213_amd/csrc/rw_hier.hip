@@ -427,6 +427,7 @@ __global__ __launch_bounds__(1024) void k_compact(const BrickGeo* __restrict__ g
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Shell sh, int lab0,
                                                     const uint8_t* __restrict__ lab,
+                                                    const float* __restrict__ x0, int64_t x0_stride,
                                                     double* __restrict__ x64, T* __restrict__ xi) {
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
@@ -438,11 +439,16 @@ __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Shell sh, int
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
                 const int gx = bt.ox + lxb, gy = bt.oy + yy, gz = bt.oz + lz;
                 const int64_t cb = ((int64_t)lz * bt.sy + yy) * bt.sx + lxb;
-                const uint8_t l = lab[bt.voff + (int64_t)gz * bt.G.plane + (int64_t)gy * bt.G.nx + gx];
+                const int64_t v = bt.voff + (int64_t)gz * bt.G.plane + (int64_t)gy * bt.G.nx + gx;
+                const uint8_t l = lab[v];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int64_t o = bt.vbase + r * bt.vstride + cb;
-                    x64[o] = l ? 0.0 : upsample(sh, lab0 + r, bt.gox + gx, bt.goy + gy, bt.goz + gz);
+                    double xv = 0.0;
+                    if (!l)
+                        xv = x0 ? (double)x0[(int64_t)(lab0 - 1 + r) * x0_stride + v]
+                                : upsample(sh, lab0 + r, bt.gox + gx, bt.goy + gy, bt.goz + gz);
+                    x64[o] = xv;
                     if (xi) xi[o] = T(0);
                 }
             }
@@ -749,9 +755,11 @@ struct BrickSolve {
         RW_HIP(hipMemcpyAsync(B.list_all, all_ids.data(), sizeof(int) * P->ntiles,
                               hipMemcpyHostToDevice, s));
         RW_HIP(hipMemcpyAsync(B.counts, cnt_all, sizeof(cnt_all), hipMemcpyHostToDevice, s));
-        // x0 = upsampled coarse solution, then the brick residuals
+        // x0 = the caller's initial guess or the upsampled coarse solution,
+        // then the brick residuals
         hipLaunchKernelGGL((k_brick_init<T, R>), dim3(grid), dim3(256), 0, s, all(), sh, lab0, lab,
-                           B.x64, mixed ? (T*)B.xi : (T*)nullptr);
+                           static_cast<const float*>(o->x0), F.n, B.x64,
+                           mixed ? (T*)B.xi : (T*)nullptr);
         hipLaunchKernelGGL((k_residual<V, T, R, BY, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, all(), sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
                            (T*)B.p0, (T*)B.p1, mixed ? (T*)B.xi : (T*)nullptr, 1, B.st, B.part);

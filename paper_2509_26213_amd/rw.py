@@ -455,6 +455,11 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
     ctx = ctx or default_context()
     if kw.get("update_delta") is None:
         kw["update_delta"] = BRICK_UPDATE_DELTA
+    x0 = kw.get("x0")
+    if x0 is not None:
+        # initial guess in the layout of prob_out: [K][grid] float32
+        assert tuple(x0.shape) == (K,) + tuple(vol.shape), "x0 must be [K][grid]"
+        kw["x0"] = x0.to(torch.float32).contiguous()
     V = make_volume(vol, lo, hi)
     S = _seeds(labels, K)
     o = options(beta, tol, precision, **kw)
@@ -559,6 +564,83 @@ def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offse
         return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
                           evaluated=want, brick_iters=iters, brick_stats=bst)
     return prob
+
+
+def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, prev_info,
+                            levels=2, brick=(64, 64, 64), offset=(0, 0, 0), tol=1e-6,
+                            coarse_precision="fp64", brick_precision="mixed", lo=None, hi=None,
+                            lo_thr=0.02, hi_thr=0.98, change_tol=1e-4, ctx=None,
+                            level_dtype=torch.float64):
+    """Warm-started re-solve of a hierarchical solution after seeds changed.
+
+    prev_prob / prev_info: the result of hierarchical_solve(..., return_info=
+    True) with old_labels and the same levels, brick grid and thresholds.  The
+    coarse level is re-solved from the previous coarse solution; a brick is
+    re-solved (from its previous fine solution) or re-filled when it holds an
+    edited voxel, when its activity changed, or when the coarse solution
+    under it (its coarse footprint and one cell around) moved by more than
+    change_tol; every other brick keeps its previous values.  Those differ from
+    a full re-solve by at most about change_tol: a brick's solution depends on
+    its Dirichlet data through a maximum principle.  Returns (prob, info) with
+    info["resolved"] / info["refilled"] the brick indices that were redone."""
+    import numpy as np
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    g, lab = vol, new_labels
+    glo, ghi = V.norm_lo, V.norm_hi
+    for _ in range(levels):
+        g, lab = downsample(g, lab, lo=glo, hi=ghi, out_dtype=level_dtype, ctx=ctx)
+        glo, ghi = 0.0, 1.0
+    old_coarse = prev_info["coarse"]
+    x0 = old_coarse[1:].to(torch.float64)  # hierarchical_solve solves labels 2..K
+    coarse, _, cst = solve(g, lab, K, beta, tol=tol, precision=coarse_precision, lo=0.0, hi=1.0,
+                           argmax=False, ctx=ctx, return_stats=True, x0=x0)
+    f = 2 ** levels
+    cands, active = classify_bricks(coarse, new_labels, f, brick, offset, lo_thr, hi_thr, ctx=ctx)
+    assert [tuple(map(tuple, b)) for b in cands] == [tuple(map(tuple, b)) for b in
+                                                      prev_info["bricks"]], "brick grid changed"
+    # bricks holding an edited voxel
+    edits = torch.nonzero(old_labels != new_labels).cpu().numpy()
+    cuts = []
+    for a in range(3):
+        starts = sorted({int(o[a]) for o, _ in cands})
+        cuts.append(np.array(starts))
+    n_axis = [len(c) for c in cuts]
+    edited = set()
+    dims = tuple(vol.shape)
+    steps = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))
+    for e in edits:
+        # the brick holding the voxel and the bricks whose shell it lies in
+        for d in steps:
+            p = [int(e[a]) + d[a] for a in range(3)]
+            if any(v < 0 or v >= n for v, n in zip(p, dims)):
+                continue
+            i = [int(np.searchsorted(cuts[a], p[a], side="right") - 1) for a in range(3)]
+            edited.add((i[0] * n_axis[1] + i[1]) * n_axis[2] + i[2])
+    # how far the coarse solution moved under each brick
+    dc = (coarse.double() - old_coarse.double()).abs().amax(0).cpu().numpy()
+    cshape = dc.shape
+    moved = []
+    for o, s in cands:
+        sl = tuple(slice(max(0, oo // f - 1), min(n, -(-(oo + ss) // f) + 1))
+                   for oo, ss, n in zip(o, s, cshape))
+        moved.append(float(dc[sl].max()))
+    prob = prev_prob.clone()
+    redo = [i for i in range(len(cands))
+            if i in edited or active[i] != prev_info["active"][i] or moved[i] > change_tol]
+    solve_ids = [i for i in redo if active[i]]
+    fill_ids = [i for i in redo if not active[i]]
+    if fill_ids:
+        fill_bricks(coarse, new_labels, f, [cands[i] for i in fill_ids], prob, ctx=ctx)
+    bst, iters = None, []
+    if solve_ids:
+        _, iters, bst = solve_bricks(vol, new_labels, K, beta, coarse, f,
+                                     [cands[i] for i in solve_ids], prob_out=prob, tol=tol,
+                                     precision=brick_precision, lo=V.norm_lo, hi=V.norm_hi,
+                                     ctx=ctx, return_stats=True, x0=prev_prob)
+    return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
+                      resolved=solve_ids, refilled=fill_ids, brick_iters=iters, brick_stats=bst,
+                      coarse_moved=moved)
 
 
 # ---------------------------------------------------------------- gradients

@@ -252,3 +252,39 @@ def test_region_of_interest_equals_full_solve(rw, case, roi):
         if not e:
             bs = tuple(slice(a, a + b) for a, b in zip(o, s))
             assert not bool(part[:, bs[0], bs[1], bs[2]].any())
+
+
+def test_seed_edit_resolve_matches_full_solve(rw, case):
+    """Interactive seed edit: the warm-started re-solve redoes only the bricks
+    the edit reaches (holding or bordering an edited voxel, or whose coarse
+    data moved by more than change_tol), keeps the others bit for bit, and
+    agrees with a full re-solve to change_tol (kept bricks, maximum principle)
+    and to the solver tolerance on the redone ones."""
+    import torch
+    brick, offset = (16, 16, 16), (5, 3, 7)
+    kw = dict(levels=2, brick=brick, offset=offset, tol=1e-8, coarse_precision="fp64",
+              brick_precision="mixed")
+    vol, lab = dev(case.vol), dev(case.labels)
+    prev, pinfo = rw.hierarchical_solve(vol, lab, 3, case.beta, return_info=True, **kw)
+    new = case.labels.copy()
+    blk = new[30:33, 20:23, 40:43]
+    blk[blk == 0] = 3
+    assert (new != case.labels).sum() > 0
+    newd = dev(new)
+    full, _ = rw.hierarchical_solve(vol, newd, 3, case.beta, return_info=True, **kw)
+    inc, info = rw.resolve_after_seed_edit(vol, lab, newd, 3, case.beta, prev, pinfo,
+                                           change_tol=1e-4, **kw)
+    assert len(info["resolved"]) >= 1
+    redo = set(info["resolved"]) | set(info["refilled"])
+    P, F, Q = host(inc), host(full), host(prev)
+    for i, (o, s) in enumerate(info["bricks"]):
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        a, f, q = P[:, sl[0], sl[1], sl[2]], F[:, sl[0], sl[1], sl[2]], Q[:, sl[0], sl[1], sl[2]]
+        if i in redo:
+            assert np.max(np.abs(a - f)) <= 1e-5, (i, np.max(np.abs(a - f)))
+        else:
+            assert np.array_equal(a, q), i
+            assert np.max(np.abs(a - f)) <= 1e-4 + 1e-5, (i, np.max(np.abs(a - f)))
+    seeded = new > 0
+    for s_ in (1, 2, 3):
+        assert np.all(P[s_ - 1][seeded] == (new[seeded] == s_))
