@@ -458,7 +458,9 @@ def solve_bricks(vol, labels, K, beta, coarse_prob, factor, bricks, prob_out=Non
     x0 = kw.get("x0")
     if x0 is not None:
         # initial guess in the layout of prob_out: [K][grid] float32
-        assert tuple(x0.shape) == (K,) + tuple(vol.shape), "x0 must be [K][grid]"
+        if tuple(x0.shape) != (K,) + tuple(vol.shape):
+            raise ValueError(f"x0 must be [K][grid] = {(K,) + tuple(vol.shape)}, got "
+                             f"{tuple(x0.shape)}")
         kw["x0"] = x0.to(torch.float32).contiguous()
     V = make_volume(vol, lo, hi)
     S = _seeds(labels, K)
@@ -597,8 +599,9 @@ def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, pre
                            argmax=False, ctx=ctx, return_stats=True, x0=x0)
     f = 2 ** levels
     cands, active = classify_bricks(coarse, new_labels, f, brick, offset, lo_thr, hi_thr, ctx=ctx)
-    assert [tuple(map(tuple, b)) for b in cands] == [tuple(map(tuple, b)) for b in
-                                                      prev_info["bricks"]], "brick grid changed"
+    if [tuple(map(tuple, b)) for b in cands] != [tuple(map(tuple, b)) for b in
+                                                  prev_info["bricks"]]:
+        raise ValueError("the brick grid differs from the previous solve's")
     # bricks holding an edited voxel
     edits = torch.nonzero(old_labels != new_labels).cpu().numpy()
     cuts = []

@@ -54,7 +54,8 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
     (None: the brick default).  Returns (out, info dict with timings and
     counts).
     """
-    assert all(b % 2 == 0 for b in brick), "brick sizes must be even"
+    if not all(b % 2 == 0 for b in brick):
+        raise ValueError("brick sizes must be even")
     ctx = ctx or rw.default_context()
     dev = torch.device("cuda")
     shape = tuple(int(s) for s in vol_host.shape)
