@@ -456,11 +456,10 @@ __global__ __launch_bounds__(256) void k_brick_init(BrickTiles ts, Shell sh, int
     }
 }
 
-// x64 += xi, xi = 0 on the unknowns of the listed tiles, for the labels
+// x64 += xi, xi = 0 on the cells of the listed tiles, for the labels
 // flagged for a refresh (all labels when all = 1).
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts,
-                                                    const uint8_t* __restrict__ lab,
                                                     const RhsState* __restrict__ st,
                                                     double* __restrict__ x64, T* __restrict__ xi,
                                                     int all) {
@@ -473,13 +472,13 @@ __global__ __launch_bounds__(256) void k_brick_fold(BrickTiles ts,
         for (int r = 0; r < R; ++r)
             if (all || st[bt.sidx * R + r].outer_active == 2) mask |= 1 << r;
         if (!mask) continue;
+        // seeds need no test: xi is 0 there (never written but as 0), so
+        // x64 keeps its value and the loads of a column pipeline freely
         const int lxb = bt.X0 + (threadIdx.x & 63);
         for (int yy = bt.Y0 + (threadIdx.x >> 6); yy < min(bt.Y0 + ts.by, bt.sy); yy += 4) {
             if (lxb >= bt.sx) break;
+#pragma unroll 4
             for (int lz = bt.z0; lz < bt.z1; ++lz) {
-                const int64_t g = bt.voff + (int64_t)(bt.oz + lz) * bt.G.plane +
-                                  (int64_t)(bt.oy + yy) * bt.G.nx + bt.ox + lxb;
-                if (lab[g]) continue;
                 const int64_t cb = ((int64_t)lz * bt.sy + yy) * bt.sx + lxb;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -732,7 +731,7 @@ struct BrickSolve {
     rw_status refresh() {
         hipStream_t s = ctx->s;
         const BrickTiles tr = ref();
-        hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, lab, B.st,
+        hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, tr, B.st,
                            B.x64, (T*)B.xi, 0);
         hipLaunchKernelGGL((k_residual<V, T, R, BY, BVX, BrickTiles, YM>), dim3(grid), dim3(64, BY), 0, s,
                            vol, lab, wc, tr, sh, lab0, B.x64, (const double*)nullptr, (T*)B.z,
@@ -834,7 +833,7 @@ struct BrickSolve {
         if (e) return e;
         RW_HIP(e2);
         if (mixed)
-            hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, all(), lab, B.st,
+            hipLaunchKernelGGL((k_brick_fold<T, R>), dim3(grid), dim3(256), 0, s, all(), B.st,
                                B.x64, (T*)B.xi, 1);
         RW_HIP(hipGetLastError());
         return RW_OK;

@@ -181,13 +181,12 @@ __global__ void k_mark_refresh(RhsState* __restrict__ st, int mask) {
     if (r < R && (mask & (1 << r))) st[r].outer_active = 2;
 }
 
-// x64 += xi, xi = 0 on the unseeded voxels of the labels in `mask`.
+// x64 += xi, xi = 0 for the labels in `mask`.  Seeds need no test: xi is 0
+// there (never written but as 0), so their x64 keeps its value.
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_update64(const uint8_t* __restrict__ lab, int64_t n,
-                                                  T* __restrict__ xi, double* __restrict__ x64,
-                                                  int mask) {
+__global__ __launch_bounds__(256) void k_update64(int64_t n, T* __restrict__ xi,
+                                                  double* __restrict__ x64, int mask) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
-        if (lab[i] != 0) continue;
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (mask & (1 << r)) {
@@ -378,7 +377,7 @@ struct WholeSolve {
     // residual of the labels in `mask` in float64.
     rw_status refresh(int mask) {
         hipLaunchKernelGGL((k_mark_refresh<R>), dim3(1), dim3(64), 0, ctx->s, B.st, mask);
-        hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, ctx->s, lab, G.n,
+        hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, ctx->s, G.n,
                            (T*)B.xi, B.x64, mask);
         rw_status e = launch_residual(2);
         if (e) return e;
@@ -525,7 +524,7 @@ struct WholeSolve {
             if ((e = inner())) return e;
             // labels stopped by the iteration cap still hold their last
             // correction in xi
-            hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, s, lab, G.n,
+            hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, s, G.n,
                                (T*)B.xi, B.x64, (1 << R) - 1);
             RW_HIP(hipGetLastError());
             return RW_OK;
@@ -544,7 +543,7 @@ struct WholeSolve {
             for (int r = 0; r < R; ++r)
                 if (host_st[r].active) mask |= 1 << r;
             if ((e = inner())) return e;
-            hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, s, lab, G.n,
+            hipLaunchKernelGGL((k_update64<T, R>), dim3(grid1d(G.n)), dim3(256), 0, s, G.n,
                                (T*)B.xi, B.x64, mask);
             RW_HIP(hipGetLastError());
             for (int r = 0; r < R; ++r) host_st[r].refreshes += (mask >> r) & 1;
