@@ -738,15 +738,16 @@ struct XCell {
     double xt[R];
     bool dir;
 
+    // lmask: the labels whose values are wanted (the others are left 0).
     __device__ __forceinline__ void make(double gv, uint8_t lb, const double (&xb)[R], bool in_vol,
                                          bool in_box, const Shell& sh, int lab0, int gx, int gy,
-                                         int gz) {
+                                         int gz, int lmask) {
         g = in_vol ? (GT)gv : GT(0);
         dir = !(in_box && lb == 0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double v = 0.0;
-            if (!in_vol) v = 0.0;
+            if (!in_vol || !(lmask & (1 << r))) v = 0.0;
             else if (lb != 0) v = (lab0 > 0 && lb == lab0 + r) ? 1.0 : 0.0;
             else if (in_box) v = xb[r];
             else if (sh.coarse && lab0 > 0) v = upsample(sh, lab0 + r, gx, gy, gz);
@@ -795,6 +796,9 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 if (st[bt.sidx * R + r].outer_active == 2) wmask |= 1 << r;
             if (!wmask) continue;  // uniform over the block
         }
+        // labels computed: a refresh (mode 2) needs only the flagged ones,
+        // whose partials alone are read back
+        const int lmask = mode == 2 ? wmask : (1 << R) - 1;
         Lanes L;
         L.init(G, bt);
         const int64_t bplane = (int64_t)bt.sx * bt.sy;
@@ -816,7 +820,8 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
             w.lb = ldu(lab + ov, cv);
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                w.xb[r] = x64 ? ldu(x64 + bt.vbase + r * bt.vstride + ob, cb) : 0.0;
+                w.xb[r] = x64 && (lmask & (1 << r)) ? ldu(x64 + bt.vbase + r * bt.vstride + ob, cb)
+                                                    : 0.0;
         };
         auto load_own = [&](int lz, Raw (&w)[VX]) {
             const PlaneOff o = plane_off(G, bt, lz);
@@ -839,7 +844,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
             for (int v = 0; v < VX; ++v) {
                 lb[v] = w[v].lb;
                 c[v].make((double)w[v].g, w[v].lb, w[v].xb, L.in_vol[v] && zvol, L.in_box[v] && inb,
-                          sh, lab0, bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz);
+                          sh, lab0, bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz, lmask);
             }
         };
 
@@ -863,7 +868,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
             make_own(lz + 1, own1, cp, lbp);
             XCell<GT, R> hx;
             hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
-                    bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz);
+                    bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz, lmask);
             XCell<GT, R> hy[NYH][HV];
 #pragma unroll
             for (int j = 0; j < NYH; ++j)
@@ -871,7 +876,8 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 for (int h = 0; h < HV; ++h)
                     hy[j][h].make((double)hy0[j][h].g, hy0[j][h].lb, hy0[j][h].xb,
                                   L.hy_vol[j][h] && zvol, L.hy_box[j][h] && inb, sh, lab0,
-                                  bt.gox + L.gx[0] + 64 * h, bt.goy + L.hy_gy[j], bt.goz + gz);
+                                  bt.gox + L.gx[0] + 64 * h, bt.goy + L.hy_gy[j], bt.goz + gz,
+                                  lmask);
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
@@ -958,6 +964,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 const T dinv = T(1) / dT;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    if (!(lmask & (1 << r))) continue;  // uniform over the block
                     const int64_t vb = bt.vbase + r * bt.vstride + ob;
                     double xn[6];
 #pragma unroll

@@ -133,12 +133,15 @@ __global__ __launch_bounds__(256) void k_build_weights(const V* __restrict__ vol
 
 // ------------------------------------------------------------------ helpers
 
-rw_status check_volume(const rw_volume* vol) {
+rw_status check_volume(const rw_volume* vol, bool pool) {
     if (!vol) return invalid("volume is NULL");
     if (!vol->data) return invalid("volume data is NULL");
     if (vol->dims.nx <= 0 || vol->dims.ny <= 0 || vol->dims.nz <= 0)
         return invalid("volume dimensions must be positive");
-    if (!dims_supported(vol->dims))
+    const int64_t lim = int64_t(1) << 40;
+    const rw_dims& d = vol->dims;
+    const bool pool_ok = d.nx <= lim && d.ny <= lim / d.nx && d.nz <= lim / (d.nx * d.ny);
+    if (pool ? !pool_ok : !dims_supported(d))
         return invalid("volume too large (sides at most 2^30, nx * ny at most 2^29, "
                        "nx * ny * nz at most 2^40 voxels)");
     if (vol->dtype != RW_DT_U16 && vol->dtype != RW_DT_F32 && vol->dtype != RW_DT_F64)

@@ -1114,6 +1114,8 @@ static rw_status check_subvolumes(const rw_brick* bricks, const rw_subvolume* su
     const int64_t total = pool.nx * pool.ny * pool.nz;
     for (int i = 0; i < n; ++i) {
         const rw_subvolume& v = sub[i];
+        if (!dims_supported(rw_dims{v.nx, v.ny, v.nz}))
+            return invalid("sub-volume " + std::to_string(i) + " is too large");
         if (v.nx < 1 || v.ny < 1 || v.nz < 1 || v.offset < 0 ||
             v.offset + (int64_t)v.nx * v.ny * v.nz > total || v.gx < 0 || v.gy < 0 || v.gz < 0)
             return invalid("sub-volume " + std::to_string(i) + " does not fit the pool");
@@ -1132,7 +1134,7 @@ rw_status rw_solve_bricks(rw_context* ctx, const rw_volume* fine, const rw_seeds
                           int32_t* brick_iters, void* ws, size_t ws_bytes, rw_stats* stats,
                           void* stream) {
     if (!ctx || !prob_out) return invalid("NULL argument");
-    rw_status e = check_volume(fine);
+    rw_status e = check_volume(fine, subvols != nullptr);
     if (e) return e;
     if ((e = check_options(o))) return e;
     if (!seeds || !seeds->labels) return invalid("seeds are NULL");

@@ -7,7 +7,9 @@
 namespace rw {
 
 rw_status invalid(const std::string& msg);
-rw_status check_volume(const rw_volume* vol);
+// pool: the volume is a flat pool of brick sub-volumes (dims (n, 1, 1)), which
+// the kernels address per sub-volume, so only its total size is limited.
+rw_status check_volume(const rw_volume* vol, bool pool = false);
 // Grids the kernels can address: every side in [1, 2^30], a plane of at most
 // 2^29 voxels (in-plane offsets are 32-bit byte offsets of 8-byte values)
 // and at most 2^40 voxels (tile counts are 32-bit).
