@@ -19,6 +19,10 @@ algorithmic bytes per launch over its average launch duration from HIP
 events recorded around every launch on the library's stream.  `cpu_baseline`
 is the C/OpenMP float64 oracle timed on a bounded sample of the same
 workload.
+
+Other workloads (`--workload`): hier1024 (hierarchical batched bricks),
+stream2048 (bricks streamed through device pools), sphere128grad (float64
+forward + adjoint gradient); each is described in its own function.
 """
 from __future__ import annotations
 
@@ -226,6 +230,8 @@ def main():
         return bench_hier(args)
     if args.workload == "stream2048":
         return bench_stream(args)
+    if args.workload == "sphere128grad":
+        return bench_grad(args)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     case = make_workload(args.workload)
@@ -452,6 +458,54 @@ def bench_hier(args):
         / 1e9 / HBM_PEAK_GBS,
         "coarse": {"iters": og["coarse"]["iters"], "device_ms": og["coarse"]["device_ms"]},
         "cpu_baseline": cpu,
+    }), flush=True)
+
+
+def bench_grad(args):
+    """Differentiable solve (128^3 float32 sphere, sigma 0.1, 500 seeds per
+    label, beta 120): one step = the float64 forward solve of the foreground
+    label and the adjoint solve + edge-gradient kernel giving dL/dg and
+    dL/dbeta of L = sum (x_fg - mask)^2, both at tol 1e-6."""
+    import numpy as np
+    import torch
+    from paper_2509_26213_amd import rw
+    from synth import sphere_case
+    dev = torch.device("cuda:0")
+    c = sphere_case(n=128, radius=40, sigma=0.1, seed_radius=20, corner=16, n_seeds=500,
+                    beta=120.0, seed=4)
+    lo, hi = c.norm_range()
+    g = ((torch.from_numpy(c.vol).to(dev).double() - lo) / (hi - lo)).contiguous()
+    lab = torch.from_numpy(c.labels).to(dev)
+    mask = torch.from_numpy(c.truth.astype(np.float64)).to(dev)
+    n_vox = int(np.prod(c.vol.shape))
+
+    def step():
+        t0 = time.perf_counter()
+        prob, _, fst = rw.solve(g, lab, 2, c.beta, tol=1e-6, precision="fp64", lo=0.0, hi=1.0,
+                                argmax=False, return_stats=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dg, db = rw.solve_backward(g, lab, 2, c.beta, 2, prob[1], 2 * (prob[1] - mask), tol=1e-6)
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1, fst, db
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    outs = [step() for _ in range(args.steps)]
+    fwd = float(np.median([o[0] for o in outs]))
+    bwd = float(np.median([o[1] for o in outs]))
+    print(json.dumps({
+        "metric": METRIC, "value": n_vox / (fwd + bwd), "unit": "voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": (fwd + bwd) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sphere128grad: 128^3 float32 sphere (radius 40 at 0.7 on 0.3, "
+                               "sigma 0.1), K=2, 500 seeds per label, beta 120, loss "
+                               "sum (x_fg - mask)^2, float64 forward + adjoint, tol 1e-6",
+                   "voxels": n_vox},
+        "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
+        "forward_iters": outs[-1][2]["iters"], "dL_dbeta": outs[-1][3],
     }), flush=True)
 
 
