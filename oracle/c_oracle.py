@@ -47,6 +47,9 @@ def lib():
         L.orc_residual.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P,
                                    ctypes.c_int]
         L.orc_residual.restype = ctypes.c_double
+        L.orc_adjoint_grad.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, P, P,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, P, P]
+        L.orc_adjoint_grad.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -142,3 +145,25 @@ def residual(g, labels, label, beta, x, w_eps=0.0, nthreads=0):
     dims = np.array([nx, ny, nz], dtype=np.int64)
     return float(lib().orc_residual(_p(g), _p(labels), _p(dims), float(beta), float(w_eps),
                                     int(label), _p(x), int(nthreads)))
+
+
+def adjoint_gradient(g, labels, beta, x_full, dLdx, tol=1e-12, max_iter=200000, w_eps=0.0,
+                     nthreads=0):
+    """dL/dbeta and dL/dg of a loss of one label's whole-volume solution x_full
+    (seeds exact) with dL/dx = dLdx: the adjoint system L_U lam = dL/dx_U solved
+    by the oracle's Jacobi-PCG to `tol`, then the per-edge sums.  Returns
+    (dL/dbeta, dL/dg [nz][ny][nx], lam, iterations, status)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    x_full = np.ascontiguousarray(x_full, dtype=np.float64)
+    dLdx = np.ascontiguousarray(dLdx, dtype=np.float64)
+    nz, ny, nx = g.shape
+    dims = np.array([nx, ny, nz], dtype=np.int64)
+    lam = np.empty(g.shape)
+    dg = np.empty(g.shape)
+    db = ctypes.c_double(0.0)
+    it = ctypes.c_int(0)
+    st = lib().orc_adjoint_grad(_p(g), _p(labels), _p(dims), float(beta), float(w_eps),
+                                _p(x_full), _p(dLdx), float(tol), int(max_iter), int(nthreads),
+                                _p(lam), _p(dg), ctypes.byref(db), ctypes.byref(it))
+    return db.value, dg, lam, it.value, st

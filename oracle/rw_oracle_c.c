@@ -92,15 +92,14 @@ int orc_box_weights(const double* g, const int64_t dims[3], const int64_t box[6]
     return 0;
 }
 
-/* Solve one label on a box.  shell: Dirichlet value of every non-seed voxel
- * of the one-voxel frame around the box, [(sz+2)][(sy+2)][(sx+2)] (frame
- * coordinates = box coordinates + 1), or NULL when the box is the volume.
- * x0: initial guess on the box (read on unknowns only) or NULL for 0.
- * x_out: box values, seeds set to [label == s]. */
-int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
-                  const int64_t box[6], const double* shell, double beta, double w_eps,
-                  int label, const double* x0, double tol, int max_iter, int nthreads,
-                  double* x_out, int* iters_out, double* rel_true_out) {
+/* One label on a box by Jacobi-PCG.  b is formed from the Dirichlet data
+ * (seeds, shell) or, when rhs is given, taken from rhs on the unknowns (box
+ * layout); arguments otherwise as for orc_solve_box below. */
+static int solve_box_core(const double* g, const uint8_t* labels, const int64_t dims[3],
+                          const int64_t box[6], const double* shell, const double* rhs,
+                          double beta, double w_eps, int label, const double* x0, double tol,
+                          int max_iter, int nthreads, double* x_out, int* iters_out,
+                          double* rel_true_out) {
     geom_t G = {dims[0], dims[1], dims[2], box[0], box[1], box[2], box[3], box[4], box[5]};
     if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.sx <= 0 || G.sy <= 0 || G.sz <= 0) return -1;
     if (G.ox < 0 || G.oy < 0 || G.oz < 0 || G.ox + G.sx > G.nx || G.oy + G.sy > G.ny ||
@@ -158,7 +157,7 @@ int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
                 if (lab == 0) {
                     if (!(d > 0.0)) zero_diag = 1;
                     dinv[li] = d > 0.0 ? 1.0 / d : 0.0;
-                    b[li] = bb;
+                    b[li] = rhs ? rhs[li] : bb;
                 } else {
                     dinv[li] = 0.0;
                     b[li] = 0.0;
@@ -298,6 +297,85 @@ done:
     free(part);
     free(unk);
     return status;
+}
+
+/* Solve one label on a box.  shell: Dirichlet value of every non-seed voxel
+ * of the one-voxel frame around the box, [(sz+2)][(sy+2)][(sx+2)] (frame
+ * coordinates = box coordinates + 1), or NULL when the box is the volume.
+ * x0: initial guess on the box (read on unknowns only) or NULL for 0.
+ * x_out: box values, seeds set to [label == s]. */
+int orc_solve_box(const double* g, const uint8_t* labels, const int64_t dims[3],
+                  const int64_t box[6], const double* shell, double beta, double w_eps,
+                  int label, const double* x0, double tol, int max_iter, int nthreads,
+                  double* x_out, int* iters_out, double* rel_true_out) {
+    return solve_box_core(g, labels, dims, box, shell, NULL, beta, w_eps, label, x0, tol,
+                          max_iter, nthreads, x_out, iters_out, rel_true_out);
+}
+
+/* Adjoint gradient of a loss L(x) of one label's whole-volume solution
+ * (the plain definition, by the chain rule through L_U x = b):
+ *   adjoint system  L_U lam = dL/dx on the unknowns, lam = 0 on seeds
+ *                   (L_U is symmetric, so the forward operator serves);
+ *   per edge e = (i, j)  c_e = (lam_i - lam_j)(x_i - x_j) w_e, x with its
+ *                   Dirichlet values on seeds;
+ *   dL/dbeta = sum_e c_e (g_i - g_j)^2,
+ *   dL/dg_i  = sum over the edges of i of 2 beta c_e (g_i - g_j).
+ * The adjoint system is solved by the same Jacobi-PCG (x0 = 0) to `tol`.
+ * x_full, dLdx: [nz][ny][nx]; lam_out, grad_g_out: [nz][ny][nx] or NULL.
+ * Returns the PCG status. */
+int orc_adjoint_grad(const double* g, const uint8_t* labels, const int64_t dims[3], double beta,
+                     double w_eps, const double* x_full, const double* dLdx, double tol,
+                     int max_iter, int nthreads, double* lam_out, double* grad_g_out,
+                     double* grad_beta_out, int* iters_out) {
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx <= 0 || ny <= 0 || nz <= 0) return -1;
+    const int64_t n = nx * ny * nz;
+    const int64_t box[6] = {0, 0, 0, nx, ny, nz};
+    double* lam = (double*)malloc(sizeof(double) * n);
+    double* rhs = (double*)malloc(sizeof(double) * n);
+    double* part = (double*)calloc((size_t)nz, sizeof(double));
+    if (!lam || !rhs || !part) {
+        free(lam);
+        free(rhs);
+        free(part);
+        return -1;
+    }
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) rhs[i] = labels[i] == 0 ? dLdx[i] : 0.0;
+    /* label 0 matches no seed, so lam is 0 on every seed */
+    int st = solve_box_core(g, labels, dims, box, NULL, rhs, beta, w_eps, 0, NULL, tol, max_iter,
+                            nthreads, lam, iters_out, NULL);
+    if (st >= 0) {
+#pragma omp parallel for schedule(static)
+        for (int64_t z = 0; z < nz; ++z) {
+            double sb = 0.0;
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t xx = 0; xx < nx; ++xx) {
+                    const int64_t i = (z * ny + y) * nx + xx;
+                    double gi_sum = 0.0;
+                    for (int k = 0; k < 6; ++k) {
+                        const int64_t X = xx + DX[k], Y = y + DY[k], Z = z + DZ[k];
+                        if (X < 0 || X >= nx || Y < 0 || Y >= ny || Z < 0 || Z >= nz) continue;
+                        const int64_t j = (Z * ny + Y) * nx + X;
+                        const double dg = g[i] - g[j];
+                        const double w = exp(-beta * dg * dg) + w_eps;
+                        const double c = (lam[i] - lam[j]) * (x_full[i] - x_full[j]) * w;
+                        gi_sum += 2.0 * beta * c * dg;
+                        /* each edge once for beta: the +x, +y, +z direction */
+                        if (k == 0 || k == 2 || k == 4) sb += c * dg * dg;
+                    }
+                    if (grad_g_out) grad_g_out[i] = gi_sum;
+                }
+            part[z] = sb;
+        }
+        if (grad_beta_out) *grad_beta_out = ordered_sum(part, nz);
+        if (lam_out) memcpy(lam_out, lam, sizeof(double) * n);
+    }
+    free(lam);
+    free(rhs);
+    free(part);
+    return st;
 }
 
 /* Time per PCG iteration without convergence: run exactly n_iter iterations

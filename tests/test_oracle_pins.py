@@ -292,3 +292,65 @@ def test_sphere_case_o_same_close_to_o_exact(c_oracle):
     xe = c_oracle.random_walker(g, c.labels, 2, c.beta, tol=1e-12)
     assert np.max(np.abs(xs - xe)) < 1e-5
     assert np.max(np.abs(xe.sum(0) - 1)) < 1e-9
+
+
+# ---------------------------------------------------------------- C oracle residual
+
+def test_c_oracle_residual_hand_computed_3x3x3(c_oracle):
+    """Constant image (all weights 1), fg seed at (0,0,0), bg seed at (2,2,2),
+    x = 1/2 on every unknown: the residual b - A x = sum_j w (x_j - x_i) is
+    +1/2 at the three face neighbours of the fg seed, -1/2 at those of the bg
+    seed, 0 elsewhere, and b is 1 at the fg seed's neighbours: for label 2
+    ||r|| / ||b|| = sqrt(6/4) / sqrt(3) = sqrt(1/2); for label 1 the same by
+    symmetry.  A wrong sign of A x (b + A x) would give 3/2 at those voxels."""
+    g = np.zeros((3, 3, 3))
+    lab = np.zeros((3, 3, 3), dtype=np.uint8)
+    lab[0, 0, 0] = 2
+    lab[2, 2, 2] = 1
+    x = np.full(g.shape, 0.5)
+    for s in (1, 2):
+        assert abs(c_oracle.residual(g, lab, s, 5.0, x) - np.sqrt(0.5)) < 1e-15
+
+
+def _assembled_rel_residual(g, lab, s, beta, x):
+    sysm = O.DirichletSystem(g, lab, beta)
+    b = sysm.rhs(s)
+    xU = np.asarray(x).ravel()[sysm.U]
+    return np.linalg.norm(b - sysm.LU @ xU) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c_oracle_residual_matches_assembled(seed, c_oracle):
+    """orc_residual against the assembled ||b - L_U x|| / ||b|| for random x
+    on a ragged three-label blob volume (seed values in x are ignored)."""
+    c = blob_case(shape=(11, 14, 19), n_blobs=3, K=3, seeds_per_label=6, sigma=0.08,
+                  rmin=3, rmax=6, seed=seed)
+    g = O.case_g(c)
+    rng = np.random.default_rng(seed)
+    x = rng.random(g.shape)
+    for s in (1, 2, 3):
+        ref = _assembled_rel_residual(g, c.labels, s, c.beta, x)
+        got = c_oracle.residual(g, c.labels, s, c.beta, x)
+        assert abs(got - ref) <= 1e-12 * ref, (s, got, ref)
+    # seed values in x do not enter
+    x2 = x.copy()
+    x2[c.labels > 0] = 123.0
+    assert c_oracle.residual(g, c.labels, 2, c.beta, x2) == c_oracle.residual(g, c.labels, 2,
+                                                                               c.beta, x)
+
+
+def test_c_oracle_residual_of_exact_solution_is_zero(c_oracle):
+    """At the direct solution the residual is at rounding level, and one
+    perturbed unknown raises it to the assembled value."""
+    c = blob_case(shape=(10, 12, 15), n_blobs=3, K=3, seeds_per_label=6, sigma=0.08,
+                  rmin=3, rmax=6, seed=4)
+    g = O.case_g(c)
+    x = O.random_walker(g, c.labels, 3, c.beta, method="direct")
+    for s in (1, 2, 3):
+        assert c_oracle.residual(g, c.labels, s, c.beta, x[s - 1]) < 1e-12
+    xp = x[1].copy()
+    v = int(np.flatnonzero(c.labels.ravel() == 0)[7])
+    xp.flat[v] += 1e-3
+    ref = _assembled_rel_residual(g, c.labels, 2, c.beta, xp)
+    assert ref > 1e-6
+    assert abs(c_oracle.residual(g, c.labels, 2, c.beta, xp) - ref) <= 1e-9 * ref
