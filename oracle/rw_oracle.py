@@ -72,17 +72,24 @@ def case_g(case):
 
 
 def grid_edges(shape):
-    """Every undirected 6-neighbour edge once, as flat index pairs (i, j = i + e_axis).
+    """Every undirected grid edge once, as flat index pairs (i, j = i + e_axis),
+    for a 3-D grid [nz][ny][nx] (6-connected) or a 4-D time series
+    [nt][nz][ny][nx] (8-connected: the two neighbours along each axis).
 
-    Returns (i, j, axis) with axis 0 = x, 1 = y, 2 = z.
+    Returns (i, j, axis) with axis 0 = x (the fastest array axis), 1 = y,
+    2 = z and, in 4-D, 3 = t.
     """
-    nz, ny, nx = shape
-    idx = np.arange(nz * ny * nx, dtype=np.int64).reshape(shape)
+    shape = tuple(int(n) for n in shape)
+    idx = np.arange(int(np.prod(shape)), dtype=np.int64).reshape(shape)
+    nd = len(shape)
     ii, jj, aa = [], [], []
-    for axis, (a, b) in enumerate((
-            (idx[:, :, :-1], idx[:, :, 1:]),
-            (idx[:, :-1, :], idx[:, 1:, :]),
-            (idx[:-1, :, :], idx[1:, :, :]))):
+    for axis in range(nd):
+        ax = nd - 1 - axis  # array axis of grid axis `axis`
+        lo = [slice(None)] * nd
+        hi = [slice(None)] * nd
+        lo[ax] = slice(None, -1)
+        hi[ax] = slice(1, None)
+        a, b = idx[tuple(lo)], idx[tuple(hi)]
         ii.append(a.ravel())
         jj.append(b.ravel())
         aa.append(np.full(a.size, axis, dtype=np.int8))

@@ -12,4 +12,5 @@ from .volumes import (  # noqa: F401
     brickwise_blob_case,
     random_case,
     splitmix64,
+    timeseries_case,
 )

@@ -324,3 +324,52 @@ class brickwise_blob_case:
         inb = (z >= oz) & (z < oz + sz) & (y >= oy) & (y < oy + sy) & (x >= ox) & (x < ox + sx)
         labels[z[inb] - oz, y[inb] - oy, x[inb] - ox] = self.seed_lab[lo:][inb]
         return vol, labels, cmap
+
+
+# --------------------------------------------------------------------------
+# volume time series (4-D random walker)
+# --------------------------------------------------------------------------
+
+def timeseries_case(shape=(200, 50, 224, 224), radius=(14.0, 40.0, 40.0), amplitude=0.25,
+                    fg=0.7, bg=0.3, sigma=0.05, fg_seeds_first=10, bg_seeds_first=10,
+                    fg_seeds_last=4, beta=100.0, seed=6, name="heart4d"):
+    """A volume time series [nt][nz][ny][nx] standing in for a cardiac MRI
+    sequence: an ellipsoid at the centre of every time step whose radii
+    (rz, ry, rx) pulse as r (1 + amplitude sin(2 pi t / nt)), intensity fg on
+    bg, additive Gaussian noise sigma.  Two labels: label 2 (foreground) seeds
+    inside the ellipsoid at half its radii, label 1 (background) seeds outside
+    1.5 times its radii; fg_seeds_first and bg_seeds_first seeds in time step
+    0, fg_seeds_last foreground seeds in the last time step.  float32."""
+    rng = np.random.default_rng(seed)
+    nt, nz, ny, nx = shape
+    cz, cy, cx = (nz - 1) / 2.0, (ny - 1) / 2.0, (nx - 1) / 2.0
+    z, y, x = np.ogrid[:nz, :ny, :nx]
+    vol = np.empty(shape, np.float32)
+    truth = np.empty(shape, bool)
+    scale = 1.0 + amplitude * np.sin(2.0 * np.pi * np.arange(nt) / nt)
+    for t in range(nt):
+        rz, ry, rx = (r * scale[t] for r in radius)
+        inside = ((z - cz) / rz) ** 2 + ((y - cy) / ry) ** 2 + ((x - cx) / rx) ** 2 <= 1.0
+        truth[t] = inside
+        vol[t] = (np.where(inside, fg, bg) + rng.normal(0.0, sigma, size=(nz, ny, nx))).astype(
+            np.float32)
+    labels = np.zeros(shape, np.uint8)
+    n3 = nz * ny * nx
+
+    def draw(t, count, lab, lo, hi):
+        rz, ry, rx = (r * scale[t] for r in radius)
+        got = 0
+        while got < count:
+            f = int(rng.integers(0, n3))
+            zz, yy, xx = _unravel(np.int64(f), (nz, ny, nx))
+            e = ((zz - cz) / rz) ** 2 + ((yy - cy) / ry) ** 2 + ((xx - cx) / rx) ** 2
+            if lo <= e <= hi and labels[t, zz, yy, xx] == 0:
+                labels[t, zz, yy, xx] = lab
+                got += 1
+
+    draw(0, fg_seeds_first, 2, 0.0, 0.25)
+    draw(0, bg_seeds_first, 1, 2.25, np.inf)
+    draw(nt - 1, fg_seeds_last, 2, 0.0, 0.25)
+    return Case(name=name, vol=vol, labels=labels, K=2, beta=beta, norm="minmax", truth=truth,
+                params=dict(shape=shape, radius=radius, amplitude=amplitude, sigma=sigma,
+                            seed=seed))
