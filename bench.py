@@ -12,7 +12,12 @@ the paper's cell-volume benchmark (Sec. IV-B, Table III).
 One step = one whole solve on inputs already resident in HBM: the device
 min-max reduction plus rw_solve in mixed precision (float32 stencil and
 vectors, float64 dot products, float64 residual refinement).  The plain
-float64 solve of the same volume is timed beside it.
+float64 solve of the same volume is timed beside it (two steps after one
+warm-up, whatever --steps is), and the same run checks the results: the
+oracle's float64 relative residual of both outputs, and mixed against
+float64 (max-abs difference, argmax away from ties).  The hierarchical
+batched workload (hier1024, see bench_hier) runs after it and is reported in
+the same line under "hier1024" (its own steps and warm-up, stated there).
 
 Prints ONE JSON line.  `roofline` is for the dominant kernel (CG pass 2):
 algorithmic bytes per launch over its average launch duration from HIP
@@ -39,6 +44,11 @@ if ROOT not in sys.path:
 METRIC = ("solved voxels/sec at rel. residual 1e-6 (FP32+FP64-dot vs FP64); "
           "% HBM roofline")
 HBM_PEAK_GBS = 8000.0
+# what roofline.traffic counts: the TCC FETCH_SIZE (scaled by a copy kernel
+# of known size) and WRITE_SIZE counters, i.e. bytes that missed the L2;
+# misses served by the memory-side cache are included, so it bounds HBM
+# bytes from above
+TRAFFIC_COUNTS = "L2-miss bytes per launch (FETCH_SIZE x copy factor + WRITE_SIZE)"
 
 
 def pass_bytes(n_vox, launches, rhs_iterations, s_g, s_m, s_v, which):
@@ -141,7 +151,8 @@ def cpu_baseline(case, gpu_iters_fp64, n_iter, threads):
     total_iters = sum(gpu_iters_fp64)
     t_solve = setup_s * len(gpu_iters_fp64) + t_iter * total_iters
     n_vox = int(np.prod(case.shape))
-    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, kind="oracle",
+    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, cpu_model=cpu_model(),
+                kind="oracle",
                 sample=(f"{it} float64 Jacobi-PCG iterations of label 2 on the full "
                         f"{case.shape[0]}^3 volume ({wall:.1f} s wall, {t_iter * 1e3:.1f} ms/iter, "
                         f"set-up {setup_s:.1f} s), scaled to the {total_iters} iterations "
@@ -181,7 +192,8 @@ def cpu_baseline_hier(case, coarse_iters, bricks, brick_iters, n_iter, threads, 
     t_bricks = float(np.mean(per_vox_iter)) * work
     n_vox = int(np.prod(case.labels.shape))
     t_solve = t_coarse + t_bricks
-    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, kind="oracle",
+    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, cpu_model=cpu_model(),
+                kind="oracle",
                 sample=(f"level-2 {g2.shape[0]}^3 solve: {it} float64 Jacobi-PCG iterations of "
                         f"label 2 scaled to the GPU's {sum(coarse_iters)}; {n_sample} of "
                         f"{len(bricks)} bricks (by size) x {n_iter} iterations, scaled by the "
@@ -198,6 +210,10 @@ def main():
     ap.add_argument("--workload", default="blob512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-hier", action="store_true",
+                    help="blob512: leave out the hier1024 sub-object")
+    ap.add_argument("--hier-steps", type=int, default=3,
+                    help="blob512: timed steps of the hier1024 sub-object")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--pool", type=int, default=256,
                     help="stream2048: bricks per device pool")
@@ -259,34 +275,42 @@ def main():
                             ctx=ctx, workspace=ws, return_stats=True, kernel_timing=timing,
                             **extra)
 
-    def timed(precision, steps, warmup):
-        """Wall time per solve over `steps` graph-replayed solves, then one
-        more solve with every pass bracketed by events (no graphs) for the
-        per-kernel rooflines."""
+    def timed(precision, steps, warmup, events=True):
+        """Wall time per solve over `steps` graph-replayed solves, then (with
+        events) one more solve with every pass bracketed by events (no
+        graphs) for the per-kernel rooflines; also the last output."""
         for _ in range(warmup):
             step(precision, False)
         torch.cuda.synchronize()
         stats = []
         t = time.perf_counter()
         for _ in range(steps):
-            stats.append(step(precision, False)[2])
+            prob, am, st = step(precision, False)
+            stats.append(st)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / steps
-        return sec, [step(precision, True)[2]]
+        if events:
+            prob, am, st = step(precision, True)
+            stats = [st]
+        return sec, stats, (prob, am)
 
-    sec_mixed, st_mixed = timed("mixed", args.steps, args.warmup)
+    sec_mixed, st_mixed, out_mixed = timed("mixed", args.steps, args.warmup)
     print(f"# mixed: {sec_mixed * 1e3:.1f} ms/step iters {st_mixed[-1]['iters']} "
           f"refinements {st_mixed[-1]['refinements']}", file=sys.stderr, flush=True)
     out_fp64 = None
+    checks = {}
     if not args.no_fp64:
-        sec_fp64, st_fp64 = timed("fp64", max(1, args.steps - 1), min(1, args.warmup))
+        sec_fp64, st_fp64, res_fp64 = timed("fp64", 2, 1, events=False)
         print(f"# fp64: {sec_fp64 * 1e3:.1f} ms/step iters {st_fp64[-1]['iters']}",
               file=sys.stderr, flush=True)
         s = st_fp64[-1]
-        b2 = pass_bytes(n_vox, s["pass_launches"][1], s["rhs_iterations"], 4, 1, 8, 2)
-        out_fp64 = dict(value=n_vox / sec_fp64, ms_per_step=sec_fp64 * 1e3, iters=s["iters"],
-                        rel_residual=s["rel_residual"],
-                        pass2_gbs=b2 / (s["pass_ms"][1] * 1e-3) / 1e9 if s["pass_ms"][1] else None)
+        out_fp64 = dict(value=n_vox / sec_fp64, ms_per_step=sec_fp64 * 1e3, steps=2, warmup=1,
+                        iters=s["iters"], rel_residual=s["rel_residual"])
+        if not args.profile_iters:
+            checks = result_checks(case, out_mixed, res_fp64)
+            print(f"# checks {checks}", file=sys.stderr, flush=True)
+        del res_fp64
+    del out_mixed
 
     # roofline of the dominant kernel (pass 2) over the timed mixed steps
     launches2 = sum(s["pass_launches"][1] for s in st_mixed)
@@ -321,6 +345,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
                      "traffic": traffic(measured_traffic("k_cg_pass2", case.name, s["tile"]),
                                         bytes2 / max(launches2, 1)),
+                     "traffic_counts": TRAFFIC_COUNTS,
                      "avg_launch_us": ms2 * 1e3 / max(launches2, 1),
                      "bytes_per_launch": bytes2 / max(launches2, 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
@@ -334,6 +359,7 @@ def main():
         "fp64": out_fp64,
         "mixed_speedup_vs_fp64": (out_fp64["value"] and (n_vox / sec_mixed) / out_fp64["value"])
         if out_fp64 else None,
+        "checks": checks,
     }
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
@@ -342,15 +368,75 @@ def main():
             result["cpu_baseline"] = cpu_baseline(case, gpu_iters, args.cpu_iters, threads)
         except Exception as e:  # the baseline never hides the GPU result
             result["cpu_baseline"] = {"error": repr(e)}
+    del vol, lab, ws
+    torch.cuda.empty_cache()
+    if args.workload == "blob512" and not args.no_hier and not args.profile_iters:
+        try:
+            result["hier1024"] = run_hier(args, args.hier_steps, 1)
+        except Exception as e:  # the sub-object never hides the headline
+            result["hier1024"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)
 
 
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def result_checks(case, out_mixed, out_fp64):
+    """Checks of this run's outputs: the oracle's float64 relative residual
+    ||b - L_U x|| / ||b|| of each solved label of both outputs (its own
+    weights from the volume, its own right-hand side from the seeds), and the
+    mixed output against the float64 one (max-abs difference, argmax
+    mismatches where the float64 top-two gap is at least 1e-4)."""
+    import numpy as np
+    import torch
+    from oracle import c_oracle, rw_oracle
+    p32, a32 = out_mixed
+    p64, a64 = out_fp64
+    top2 = torch.topk(p64, 2, dim=0).values
+    clear = (top2[0] - top2[1]) >= 1e-4
+    out = {"max_abs_mixed_vs_fp64": float((p32.double() - p64).abs().max()),
+           "argmax_mismatch_away_from_ties": int(((a32 != a64) & clear).sum()),
+           "near_ties": int((~clear).sum())}
+    del top2, clear
+    lo, hi = case.norm_range()
+    g = rw_oracle.normalize(case.vol, lo, hi)
+    for name, p in (("fp64", p64), ("mixed", p32)):
+        res = []
+        for s in range(2, case.K + 1):
+            x = p[s - 1].double().cpu().numpy()
+            res.append(c_oracle.residual(g, case.labels, s, case.beta, x))
+        out[f"oracle_rel_residual_{name}"] = res
+    out["oracle_residual_bound"] = "1e-6 (tol) for fp64; float32 rounding of the output adds to mixed"
+    return out
+
+
 def bench_hier(args):
+    """The hierarchical workload alone (see run_hier), as the JSON line."""
+    out = run_hier(args, args.steps, args.warmup)
+    line = {"metric": METRIC, "value": out.pop("value"), "unit": "voxels/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64dot", "data": "synthetic"}
+    line.update(out)
+    print(json.dumps(line), flush=True)
+
+
+def run_hier(args, steps, warmup):
     """Hierarchical workload (1024^3 u16): levels 1, 2 by device LOD steps,
     the 256^3 level solved whole (mixed), 64^3 bricks on a grid offset
     (48, 20, 40) classified from the upsampled coarse solution, the uncertain
     ones solved in one batched brick solve (mixed), the others filled.  One
-    step = the whole pipeline on the resident volume."""
+    step = the whole pipeline on the resident volume.  Returns the result
+    dict (value = volume voxels per second end to end)."""
     import warnings
 
     import numpy as np
@@ -407,13 +493,13 @@ def bench_hier(args):
         tuned = {"level2 (vx, zc, xcd, by)": list(whole), "bricks (by, rpl, zc, xcd)": list(bt)}
         del g1, l1, g2, l2, coarse
         print(f"# autotuned {tuned}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    outs = [step() for _ in range(args.steps)]
+    outs = [step() for _ in range(steps)]
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t) / args.steps
+    sec = (time.perf_counter() - t) / steps
     og = outs[-1]
     o = step(timing=True)  # per-pass events (no graphs) for the rooflines
     b = o["bricks"]
@@ -430,11 +516,10 @@ def bench_hier(args):
                                     args.cpu_iters, len(os.sched_getaffinity(0)))
         except Exception as e:  # the baseline never hides the GPU result
             cpu = {"error": repr(e)}
-    print(json.dumps({
-        "metric": METRIC, "value": n_vox / sec, "unit": "voxels/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64dot", "data": "synthetic",
+    del vol, lab
+    torch.cuda.empty_cache()
+    return {
+        "value": n_vox / sec, "ms_per_step": sec * 1e3, "steps": steps, "warmup": warmup,
         "config": {"workload": "hier1024: 1024^3 uint16 blob volume (256 blobs, 8000 seeds per "
                                "label, K=3, beta 150), level-2 256^3 solved whole, 64^3 bricks on "
                                "offset grid, uncertain bricks solved batched, mixed, tol 1e-6",
@@ -449,6 +534,7 @@ def bench_hier(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
                      "traffic": traffic(measured_traffic("k_cg_pass2", "hier1024", b["tile"]),
                                         bytes2 / max(b["pass_launches"][1], 1)),
+                     "traffic_counts": TRAFFIC_COUNTS,
                      "avg_launch_us": b["pass_ms"][1] * 1e3 / max(b["pass_launches"][1], 1),
                      "bytes_per_launch": bytes2 / max(b["pass_launches"][1], 1)},
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
@@ -458,7 +544,7 @@ def bench_hier(args):
         / 1e9 / HBM_PEAK_GBS,
         "coarse": {"iters": og["coarse"]["iters"], "device_ms": og["coarse"]["device_ms"]},
         "cpu_baseline": cpu,
-    }), flush=True)
+    }
 
 
 def bench_grad(args):
@@ -485,7 +571,9 @@ def bench_grad(args):
                                 argmax=False, return_stats=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        dg, db = rw.solve_backward(g, lab, 2, c.beta, 2, prob[1], 2 * (prob[1] - mask), tol=1e-6)
+        grad_prob = torch.stack([torch.zeros_like(mask), 2 * (prob[1] - mask)])
+        dg, db = rw.solve_backward(g, lab, 2, c.beta, prob, grad_prob, tol=1e-6)
+        db = float(db)
         torch.cuda.synchronize()
         return t1 - t0, time.perf_counter() - t1, fst, db
 

@@ -287,20 +287,34 @@ rw_status rw_fill_bricks(rw_context* ctx, const void* coarse_prob, int32_t coars
                          const rw_subvolume* subvols, int32_t n_bricks, float* prob_out,
                          void* stream);
 
-/* Adjoint gradient of a loss L(x^s) of one solved label s (float64).
- * x_full: [nz][ny][nx] the forward solution of label s (seeds exact).
- * grad_x: [nz][ny][nx] dL/dx (read on unseeded voxels).
- * Solves L_U lam = dL/dx_U with the forward operator (symmetric), then
- *   c_e = (lam_i - lam_j)(x_i - x_j) w_e,
- *   dL/dbeta = sum_e c_e (g_i - g_j)^2,
- *   dL/dg_i  = sum_{e=(i,j)} 2 beta c_e (g_i - g_j)   (g normalised).
- * grad_g_out: NULL or [nz][ny][nx] float64; grad_beta_out: NULL or host double.
- * ws: rw_backward_workspace_bytes. */
+/* Adjoint gradient of a loss L of the probabilities of a float64 rw_solve
+ * (the differentiable form of the random walker of Sec. III-A; the
+ * operator L_U is symmetric, so each adjoint system uses the forward one).
+ * prob: [K][nz][ny][nx] float64, the forward probabilities as rw_solve wrote
+ *   them with the same opts->solve_all_labels (seeds exact).
+ * grad_prob: [K][nz][ny][nx] float64, dL/dprob (read on unseeded voxels).
+ * For every solved label s (2..K, or 1..K with solve_all_labels = 1):
+ *   rhs_s = dL/dx^s, minus dL/dx^1 when label 1 is the complement 1 - sum of
+ *     the solved labels (solve_all_labels = 0: a loss of the background
+ *     reaches label s through that sum);
+ *   L_U lam_s = rhs_s on the unseeded voxels (lam_s = 0 on seeds), by the
+ *     float64 Jacobi-PCG of rw_solve to opts->tol;
+ *   c_e = (lam_i - lam_j)(x_i - x_j) w_e per edge e = (i, j);
+ * and the contributions of all solved labels add:
+ *   dL/dbeta = sum_s sum_e c_e (g_i - g_j)^2,
+ *   dL/dg_i  = sum_s sum_{e=(i,j)} 2 beta c_e (g_i - g_j)   (g normalised;
+ *     a raw-intensity gradient is dL/dg_i / (norm_hi - norm_lo)).
+ * grad_g_out: NULL or device [nz][ny][nx] float64 (overwritten).
+ * grad_beta_out: NULL or a device float64 scalar (overwritten).
+ * stats: per solved label the adjoint iterations, status and residual.
+ * Validation failures return before any device work; an adjoint solve that
+ * fails returns its status with the outputs undefined.
+ * ws: rw_backward_workspace_bytes(dims). */
 size_t rw_backward_workspace_bytes(rw_dims dims);
 rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
-                            const rw_options* opts, int32_t label, const double* x_full,
-                            const double* grad_x, double* grad_g_out, double* grad_beta_out,
-                            void* ws, size_t ws_bytes, rw_stats* stats, void* stream);
+                            const rw_options* opts, const double* prob, const double* grad_prob,
+                            double* grad_g_out, double* grad_beta_out, void* ws, size_t ws_bytes,
+                            rw_stats* stats, void* stream);
 
 /* Tile-shape autotuner of the whole-volume stencil kernels (64 vx x by
  * columns, each lane owning vx columns 64 apart, one row per wave; zc planes;

@@ -1,4 +1,4 @@
-// Adjoint gradient of a loss of one label's random-walker probabilities.
+// Adjoint gradient of a loss of the random-walker probabilities.
 //
 // Forward: A(w) x_U = b(w) with A = L_U symmetric, b from the seeds.  For a
 // loss L(x), one solve of A lam = dL/dx_U (lam = 0 on seeds) gives, per edge
@@ -6,24 +6,40 @@
 // w_e = exp(-beta (g_i - g_j)^2):
 //   dL/dbeta = sum_e (lam_i - lam_j)(x_i - x_j)(g_i - g_j)^2 w_e
 //   dL/dg_i  = sum_{e=(i,j)} 2 beta (lam_i - lam_j)(x_i - x_j)(g_i - g_j) w_e.
-// The adjoint solve reuses the forward CG kernels (float64) with an explicit
-// right-hand side and zero Dirichlet data.
+// Every solved label contributes one adjoint solve; the contributions add.
+// When the forward solve set the background (label 1) to 1 - sum of the
+// solved labels, a loss of the background reaches label s through that sum:
+// the adjoint right-hand side of label s is dL/dx^s - dL/dx^1.  The adjoint
+// solves reuse the forward CG kernels (float64) with an explicit right-hand
+// side and zero Dirichlet data.
 #include "rw_whole.h"
 
 namespace rw {
 
 constexpr int GRAD_BLOCKS = 1024;
 
+// Right-hand side of one label's adjoint system: dL/dx^s (minus dL/dx^1 when
+// label 1 is the complement of the solved labels) on unseeded voxels, 0 on
+// seeds.
+__global__ __launch_bounds__(256) void k_adjoint_rhs(const uint8_t* __restrict__ lab, int64_t n,
+                                                     const double* __restrict__ gs,
+                                                     const double* __restrict__ g1,
+                                                     double* __restrict__ rhs) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x)
+        rhs[i] = lab[i] ? 0.0 : (g1 ? gs[i] - g1[i] : gs[i]);
+}
+
 // dL/dg per voxel and per-block partial sums of dL/dbeta (each edge counted
-// once, by its low-side voxel).  gscale = 1 / (hi - lo) turns raw
-// differences into normalised ones.
+// once, by its low-side voxel) of one label; `accumulate` adds dL/dg to the
+// previous labels'.  gscale = 1 / (hi - lo) turns raw differences into
+// normalised ones.
 template <typename V>
 __global__ __launch_bounds__(256) void k_adjoint_grad(const V* __restrict__ vol,
                                                       const uint8_t* __restrict__ lab, Geom G,
                                                       WCoef wc, double gscale, double beta,
                                                       int label, const double* __restrict__ xf,
                                                       const double* __restrict__ lam,
-                                                      double* __restrict__ grad_g,
+                                                      double* __restrict__ grad_g, int accumulate,
                                                       double* __restrict__ part) {
     double acc_b = 0.0;
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < G.n; i += 256ll * gridDim.x) {
@@ -52,29 +68,36 @@ __global__ __launch_bounds__(256) void k_adjoint_grad(const V* __restrict__ vol,
             acc_g += 2.0 * beta * ce * dg;
             if (k & 1) acc_b += ce * dg * dg;  // +x, +y, +z: each edge once
         }
-        if (grad_g) grad_g[i] = acc_g;
+        if (grad_g) grad_g[i] = accumulate ? grad_g[i] + acc_g : acc_g;
     }
     double v[1] = {acc_b};
     block_sum_store<1, 4>(v, part + blockIdx.x, GRAD_BLOCKS);
 }
 
+// out = (accumulate ? out : 0) + sum of the partials, in a fixed order.
 __global__ __launch_bounds__(FIN_THREADS) void k_sum1(const double* __restrict__ part, int nb,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, int accumulate) {
     __shared__ double sums[1];
     sum_partials<1>(part, nb, sums);
-    if (threadIdx.x == 0) out[0] = sums[0];
+    if (threadIdx.x == 0) out[0] = accumulate ? out[0] + sums[0] : sums[0];
 }
 
+// One solved label: its adjoint right-hand side, adjoint solve and edge
+// sums, added to the previous labels' (slot = 0 for the first label).
 template <typename V, int VX>
 static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
-                               const rw_options* o, int label, const double* x_full,
-                               const double* grad_x, double* grad_g, double* grad_beta,
-                               void* ws, rw_stats* stats) {
+                               const rw_options* o, int label, int slot, const double* x_full,
+                               const double* grad_s, const double* grad_1, double* grad_g,
+                               double* grad_beta, void* ws, rw_stats* stats) {
     const Geom G = make_geom(vol->dims);
     Carver cv(ws);
     GroupBuffers B;
     carve_group(cv, G, 1, false, &B);
     double* gpart = cv.take<double>(GRAD_BLOCKS + 1);
+    double* rhs = cv.take<double>(G.n);
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3(GRAD_BLOCKS), dim3(256), 0, ctx->s, lab, G.n, grad_s,
+                       grad_1, rhs);
+    RW_HIP(hipGetLastError());
     const TileChoice tc = choose_tiles(G, RW_PREC_FP64, 1);
     rw_options fo = *o;
     fo.precision = RW_PREC_FP64;
@@ -89,7 +112,7 @@ static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint
     S.mixed = false;
     S.reliable = false;
     S.o = &fo;
-    S.rhs = grad_x;
+    S.rhs = rhs;
     S.B = B;
     S.zv = static_cast<double*>(B.z);
     S.p0 = static_cast<double*>(B.p0);
@@ -104,11 +127,11 @@ static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint
     else if (h.status == ST_BREAKDOWN) code = RW_ERR_BREAKDOWN;
     else if (h.status == ST_NONFINITE) code = RW_ERR_NONFINITE;
     if (stats) {
-        stats->iters[0] = h.iter_total;
-        stats->label_status[0] = code;
-        stats->rel_residual[0] = h.bb > 0 ? std::sqrt(h.rr64 / h.bb) : 0.0;
-        stats->num_solved = 1;
-        stats->loop_ms = S.loop_ms;
+        stats->iters[slot] = h.iter_total;
+        stats->label_status[slot] = code;
+        stats->rel_residual[slot] = h.bb > 0 ? std::sqrt(h.rr64 / h.bb) : 0.0;
+        stats->num_solved = slot + 1;
+        stats->loop_ms += S.loop_ms;
     }
     if (code < 0) {
         set_error("adjoint solve failed");
@@ -118,28 +141,37 @@ static rw_status backward_impl(rw_context* ctx, const rw_volume* vol, const uint
     const double gscale = span > 0 ? 1.0 / span : 0.0;
     hipLaunchKernelGGL((k_adjoint_grad<V>), dim3(GRAD_BLOCKS), dim3(256), 0, ctx->s,
                        static_cast<const V*>(vol->data), lab, G, S.wc, gscale, o->beta, label,
-                       x_full, B.x64, grad_g, gpart);
+                       x_full, B.x64, grad_g, slot > 0 ? 1 : 0, gpart);
     hipLaunchKernelGGL(k_sum1, dim3(1), dim3(FIN_THREADS), 0, ctx->s, gpart, GRAD_BLOCKS,
-                       gpart + GRAD_BLOCKS);
+                       grad_beta ? grad_beta : gpart + GRAD_BLOCKS, slot > 0 ? 1 : 0);
     RW_HIP(hipGetLastError());
-    RW_HIP(hipMemcpyAsync(ctx->host_pinned, gpart + GRAD_BLOCKS, sizeof(double),
-                          hipMemcpyDeviceToHost, ctx->s));
-    RW_HIP(hipStreamSynchronize(ctx->s));
-    if (grad_beta) memcpy(grad_beta, ctx->host_pinned, sizeof(double));
     return (rw_status)code;
 }
 
+// Every solved label in turn (labels 2..K, or 1..K with solve_all_labels).
 template <typename V>
-static rw_status backward_v(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
-                            const rw_options* o, int label, const double* x_full,
-                            const double* grad_x, double* grad_g, double* grad_beta, void* ws,
-                            rw_stats* stats) {
-    const TileChoice tc = choose_tiles(make_geom(vol->dims), RW_PREC_FP64, 1);
-    if (tc.vx == 2)
-        return backward_impl<V, 2>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
-                                   stats);
-    return backward_impl<V, 1>(ctx, vol, lab, o, label, x_full, grad_x, grad_g, grad_beta, ws,
-                               stats);
+static rw_status backward_v(rw_context* ctx, const rw_volume* vol, const uint8_t* lab, int K,
+                            const rw_options* o, const double* prob, const double* grad_prob,
+                            double* grad_g, double* grad_beta, void* ws, rw_stats* stats) {
+    const Geom G = make_geom(vol->dims);
+    const TileChoice tc = choose_tiles(G, RW_PREC_FP64, 1);
+    const int first = o->solve_all_labels ? 1 : 2;
+    const double* grad_1 = o->solve_all_labels ? nullptr : grad_prob;
+    rw_status worst = RW_OK;
+    for (int s = first; s <= K; ++s) {
+        const int slot = s - first;
+        const double* xs = prob + (int64_t)(s - 1) * G.n;
+        const double* gs = grad_prob + (int64_t)(s - 1) * G.n;
+        const rw_status e =
+            tc.vx == 2 ? backward_impl<V, 2>(ctx, vol, lab, o, s, slot, xs, gs, grad_1, grad_g,
+                                             grad_beta, ws, stats)
+                       : backward_impl<V, 1>(ctx, vol, lab, o, s, slot, xs, gs, grad_1, grad_g,
+                                             grad_beta, ws, stats);
+        if (e < 0) return e;
+        if (e > worst) worst = e;
+    }
+    RW_HIP(hipStreamSynchronize(ctx->s));
+    return worst;
 }
 
 rw_status check_options(const rw_options* o);
@@ -153,15 +185,17 @@ extern "C" {
 size_t rw_backward_workspace_bytes(rw_dims dims) {
     if (!dims_supported(dims)) return 0;
     Carver cv(nullptr);
-    carve_group(cv, make_geom(dims), 1, false, nullptr);
+    const Geom G = make_geom(dims);
+    carve_group(cv, G, 1, false, nullptr);
     cv.take<double>(GRAD_BLOCKS + 1);
+    cv.take<double>(G.n);
     return cv.bytes();
 }
 
 rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
-                            const rw_options* o, int32_t label, const double* x_full,
-                            const double* grad_x, double* grad_g_out, double* grad_beta_out,
-                            void* ws, size_t ws_bytes, rw_stats* stats, void* stream) {
+                            const rw_options* o, const double* prob, const double* grad_prob,
+                            double* grad_g_out, double* grad_beta_out, void* ws, size_t ws_bytes,
+                            rw_stats* stats, void* stream) {
     if (!ctx) return invalid("context is NULL");
     rw_status e = check_volume(vol);
     if (e) return e;
@@ -169,8 +203,9 @@ rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seed
     if (!seeds || !seeds->labels) return invalid("seeds are NULL");
     if (seeds->num_labels < 1 || seeds->num_labels > RW_MAX_LABELS)
         return invalid("num_labels must be in [1, 16]");
-    if (label < 1 || label > seeds->num_labels) return invalid("label out of range");
-    if (!x_full || !grad_x) return invalid("x_full and grad_x are required");
+    if (seeds->num_labels < 2 && !o->solve_all_labels)
+        return invalid("one label: solve_all_labels must be 1");
+    if (!prob || !grad_prob) return invalid("prob and grad_prob are required");
     const size_t need = rw_backward_workspace_bytes(vol->dims);
     if (!ws || ws_bytes < need) {
         set_error("workspace needs " + std::to_string(need) + " bytes");
@@ -185,17 +220,18 @@ rw_status rw_solve_backward(rw_context* ctx, const rw_volume* vol, const rw_seed
             (void)stream_leave(ctx, stream);
             return invalid("a seed label exceeds num_labels");
         }
+    const int K = seeds->num_labels;
     switch (vol->dtype) {
         case RW_DT_U16:
-            e = backward_v<uint16_t>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+            e = backward_v<uint16_t>(ctx, vol, seeds->labels, K, o, prob, grad_prob, grad_g_out,
                                      grad_beta_out, ws, stats);
             break;
         case RW_DT_F32:
-            e = backward_v<float>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+            e = backward_v<float>(ctx, vol, seeds->labels, K, o, prob, grad_prob, grad_g_out,
                                   grad_beta_out, ws, stats);
             break;
         default:
-            e = backward_v<double>(ctx, vol, seeds->labels, o, label, x_full, grad_x, grad_g_out,
+            e = backward_v<double>(ctx, vol, seeds->labels, K, o, prob, grad_prob, grad_g_out,
                                    grad_beta_out, ws, stats);
     }
     rw_status e2 = stream_leave(ctx, stream);

@@ -155,8 +155,8 @@ def lib():
     L.rw_backward_workspace_bytes.argtypes = [Dims]
     L.rw_backward_workspace_bytes.restype = SZ
     L.rw_solve_backward.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
-                                    ctypes.POINTER(Options), I32, P, P, P, ctypes.POINTER(D), P,
-                                    SZ, ctypes.POINTER(Stats), P]
+                                    ctypes.POINTER(Options), P, P, P, P, P, SZ,
+                                    ctypes.POINTER(Stats), P]
     L.rw_argmax.argtypes = [P, P, I32, I32, ctypes.c_int64, P, P]
     L.rw_autotune.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                               ctypes.POINTER(Options), P, P, SZ, ctypes.POINTER(I32), P]
@@ -648,32 +648,42 @@ def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, pre
 
 # ---------------------------------------------------------------- gradients
 
-def solve_backward(g, labels, K, beta, label, x_full, grad_x, tol=1e-10, lo=0.0, hi=1.0,
-                   ctx=None, **kw):
-    """Adjoint gradient (dL/dg on the normalised intensities, dL/dbeta) of a
-    loss of label `label`'s probability map x_full (float64) with dL/dx grad_x."""
+def solve_backward(g, labels, K, beta, prob, grad_prob, tol=1e-10, lo=0.0, hi=1.0,
+                   solve_all_labels=False, ctx=None, return_stats=False, **kw):
+    """Adjoint gradient of a loss of the probabilities prob [K][grid] of a
+    float64 solve (dL/dprob = grad_prob [K][grid]): returns (dL/dg on the
+    normalised intensities [grid] float64, dL/dbeta as a 0-d float64 device
+    tensor).  solve_all_labels must be the forward solve's."""
     ctx = ctx or default_context()
     V = make_volume(g, lo, hi)
     S = _seeds(labels, K)
-    o = options(beta, tol, "fp64", **kw)
-    x_full = x_full.to(torch.float64).contiguous()
-    grad_x = grad_x.to(torch.float64).contiguous()
+    o = options(beta, tol, "fp64", solve_all_labels=solve_all_labels, **kw)
+    shape = (K,) + tuple(g.shape)
+    if tuple(prob.shape) != shape or tuple(grad_prob.shape) != shape:
+        raise ValueError(f"prob and grad_prob must be [K][grid] = {shape}")
+    prob = prob.to(torch.float64).contiguous()
+    grad_prob = grad_prob.to(torch.float64).contiguous()
     grad_g = torch.empty(tuple(g.shape), dtype=torch.float64, device=g.device)
-    gb = ctypes.c_double(0.0)
+    grad_beta = torch.empty((), dtype=torch.float64, device=g.device)
     nbytes = lib().rw_backward_workspace_bytes(_dims(g.shape))
     ws = _alloc_ws(nbytes, g.device)
     st = Stats()
-    _check(lib().rw_solve_backward(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
-                                   int(label), _ptr(x_full), _ptr(grad_x), _ptr(grad_g),
-                                   ctypes.byref(gb), _ptr(ws), nbytes, ctypes.byref(st), _stream()),
-           "rw_solve_backward")
-    return grad_g, gb.value
+    status = lib().rw_solve_backward(ctx.handle, ctypes.byref(V), ctypes.byref(S),
+                                     ctypes.byref(o), _ptr(prob), _ptr(grad_prob), _ptr(grad_g),
+                                     _ptr(grad_beta), _ptr(ws), nbytes, ctypes.byref(st),
+                                     _stream())
+    _check(status, "rw_solve_backward")
+    if return_stats:
+        d = st.to_dict()
+        d["status"] = status
+        return grad_g, grad_beta, d
+    return grad_g, grad_beta
 
 
 class RandomWalkerFn(torch.autograd.Function):
     """Probabilities [K][grid] of a float64 random-walker solve of normalised
     intensities g (GPU, float64) with parameter beta; differentiable in g and
-    beta through one adjoint solve per solved label."""
+    beta through the library's adjoint solves (rw_solve_backward)."""
 
     @staticmethod
     def forward(ctx, g, beta, labels, K, tol, solve_all_labels):
@@ -687,20 +697,9 @@ class RandomWalkerFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_prob):
         g, labels, prob = ctx.saved_tensors
-        K = ctx.K
-        grad_g = torch.zeros_like(g, dtype=torch.float64)
-        grad_b = 0.0
-        solved = range(1, K + 1) if ctx.all else range(2, K + 1)
-        for s in solved:
-            gs = grad_prob[s - 1] if ctx.all else grad_prob[s - 1] - grad_prob[0]
-            if not torch.any(gs != 0):
-                continue
-            dg, db = solve_backward(g.contiguous(), labels, K, ctx.beta, s, prob[s - 1], gs,
-                                    tol=min(ctx.tol, 1e-10))
-            grad_g += dg
-            grad_b += db
-        gb = torch.tensor(grad_b, dtype=torch.float64, device=g.device)
-        return grad_g.to(g.dtype), gb, None, None, None, None
+        grad_g, grad_b = solve_backward(g.contiguous(), labels, ctx.K, ctx.beta, prob, grad_prob,
+                                        tol=min(ctx.tol, 1e-10), solve_all_labels=ctx.all)
+        return grad_g.to(g.dtype), grad_b, None, None, None, None
 
 
 def random_walker(g, beta, labels, K, tol=1e-10, solve_all_labels=False):

@@ -43,11 +43,14 @@ def _brick_grid(shape, brick):
 
 
 def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, tol=1e-6,
-                   levels=2, lo=0.0, hi=65535.0, lo_thr=0.02, hi_thr=0.98, precision="mixed",
+                   levels=2, lo=None, hi=None, lo_thr=0.02, hi_thr=0.98, precision="mixed",
                    out=None, labels_out=None, ctx=None, update_delta=None):
     """vol_host: uint16 or float32 numpy [nz][ny][nx]; lab_host: uint8 numpy.
 
     Brick sizes must be even (level-1 blocks must not straddle bricks).
+    lo, hi: the normalisation g = (v - lo) / (hi - lo); None takes 0 and
+    65535 for uint16 volumes and the volume's own minimum and maximum for
+    float32 ones.
     out: float32 [K][...] host array for the probabilities; labels_out: uint8
     [...] host array for the label map.  With neither given, probabilities
     are returned.  update_delta: the brick solves' float64 refresh threshold
@@ -57,6 +60,15 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
     if not all(b % 2 == 0 for b in brick):
         raise ValueError("brick sizes must be even")
     ctx = ctx or rw.default_context()
+    if vol_host.dtype == np.uint16:
+        lo = 0.0 if lo is None else float(lo)
+        hi = 65535.0 if hi is None else float(hi)
+    elif vol_host.dtype == np.float32:
+        # min-max normalisation over the whole level-0 volume
+        lo = float(np.min(vol_host)) if lo is None else float(lo)
+        hi = float(np.max(vol_host)) if hi is None else float(hi)
+    else:
+        raise TypeError(f"streamed volumes are uint16 or float32, not {vol_host.dtype}")
     dev = torch.device("cuda")
     shape = tuple(int(s) for s in vol_host.shape)
     tdt = torch.from_numpy(vol_host[:1, :1, :1].copy()).dtype
@@ -116,6 +128,7 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
     torch.cuda.synchronize()
     info["coarse_s"] = time.perf_counter() - t0
     info["coarse_iters"] = cst["iters"]
+    info["coarse"] = coarse
     act = [b for b, a in zip(cands, active) if a]
     ina = [b for b, a in zip(cands, active) if not a]
     info["bricks"] = len(cands)

@@ -24,7 +24,11 @@ def test_adjoint_matches_oracle_direct(rw):
     x = O.random_walker(g, c.labels, 2, 8.0, method="direct")[1]
     _, dLdx = O.seg_loss(x, mask)
     db_ref, dg_ref, _ = O.adjoint_gradient(g, c.labels, 8.0, 2, dLdx, x_full=x)
-    dg, db = rw.solve_backward(dev(g), dev(c.labels), 2, 8.0, 2, dev(x), dev(dLdx), tol=1e-13)
+    prob = np.stack([1.0 - x, x])
+    grad_prob = np.stack([np.zeros_like(x), dLdx])
+    dg, db = rw.solve_backward(dev(g), dev(c.labels), 2, 8.0, dev(prob), dev(grad_prob),
+                               tol=1e-13)
+    db = float(db)
     assert abs(db - db_ref) <= 1e-8 * max(1.0, abs(db_ref))
     assert np.max(np.abs(host(dg) - dg_ref)) <= 1e-8 * max(1.0, np.max(np.abs(dg_ref)))
 
@@ -69,8 +73,9 @@ def test_sphere_gradients_vs_central_differences(rw):
         return float(((prob[1] - md) ** 2).sum())
 
     prob, _ = rw.solve(gd, lab, 2, 120.0, tol=1e-12, precision="fp64", lo=0.0, hi=1.0)
-    dLdx = 2 * (prob[1] - md)
-    dg, db = rw.solve_backward(gd, lab, 2, 120.0, 2, prob[1], dLdx, tol=1e-12)
+    grad_prob = torch.stack([torch.zeros_like(md), 2 * (prob[1] - md)])
+    dg, db = rw.solve_backward(gd, lab, 2, 120.0, prob, grad_prob, tol=1e-12)
+    db = float(db)
     h = 1e-4
     fd_b = (loss(gd, 120.0 + h) - loss(gd, 120.0 - h)) / (2 * h)
     assert abs(fd_b - db) <= 1e-4 * max(abs(fd_b), 1e-12), (fd_b, db)

@@ -56,6 +56,7 @@ def test_sphere128_gradients_vs_central_differences(rw):
     sum (x_fg - mask)^2: adjoint dL/dbeta (h 1e-4) and dL/dg on 64 sampled
     voxels (h 1e-3; 32 near the sphere surface, 32 uniform) against central
     differences of float64 solves at tol 1e-12 from x0 = 0."""
+    import torch
     from oracle import rw_oracle
     c = sphere_case(n=128, radius=40, sigma=0.1, seed_radius=20, corner=16, n_seeds=500,
                     beta=120.0, seed=4)
@@ -68,7 +69,9 @@ def test_sphere128_gradients_vs_central_differences(rw):
         return float(((prob[1] - md) ** 2).sum())
 
     prob, _ = rw.solve(gd, lab, 2, 120.0, tol=1e-12, precision="fp64", lo=0.0, hi=1.0)
-    dg, db = rw.solve_backward(gd, lab, 2, 120.0, 2, prob[1], 2 * (prob[1] - md), tol=1e-12)
+    grad_prob = torch.stack([torch.zeros_like(md), 2 * (prob[1] - md)])
+    dg, db = rw.solve_backward(gd, lab, 2, 120.0, prob, grad_prob, tol=1e-12)
+    db = float(db)
     h = 1e-4
     fd_b = (loss(gd, 120.0 + h) - loss(gd, 120.0 - h)) / (2 * h)
     assert abs(fd_b - db) <= 1e-4 * abs(fd_b), (fd_b, db)

@@ -34,6 +34,24 @@ def test_streamed_equals_resident(rw):
     assert info["h2d_bytes"] > c.vol.nbytes
 
 
+def test_streamed_float32_normalises_like_resident(rw):
+    """A float32 volume streamed without an explicit range is min-max
+    normalised over the whole volume, as the resident pipeline does: the two
+    give bitwise the same probabilities."""
+    import torch
+    from paper_2509_26213_amd.stream import streamed_solve
+    c = blob_case(shape=(48, 64, 70), n_blobs=6, K=3, seeds_per_label=30, sigma=0.06, rmin=5,
+                  rmax=12, seed=45, dtype="f32")
+    prob_s, info = streamed_solve(c.vol, c.labels, 3, c.beta, brick=(32, 32, 32), pool=2,
+                                  tol=1e-6, levels=2, precision="mixed")
+    prob_r = rw.hierarchical_solve(dev(c.vol), dev(c.labels), 3, c.beta, levels=2,
+                                   brick=(32, 32, 32), offset=(0, 0, 0), tol=1e-6,
+                                   coarse_precision="mixed", brick_precision="mixed",
+                                   level_dtype=torch.float32)
+    assert info["active_bricks"] >= 2
+    assert np.array_equal(prob_s, host(prob_r))
+
+
 def test_streamed_labels_only(rw):
     """Labels-only output (device argmax, uint8 over PCIe) equals the argmax
     of the streamed probabilities, lowest label on ties."""
