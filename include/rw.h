@@ -214,6 +214,23 @@ rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                    const rw_options* opts, void* prob_out, uint8_t* argmax_out, void* ws,
                    size_t ws_bytes, rw_stats* stats, void* stream);
 
+/* rw_solve without device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The workspace is a static device array of
+ * rw_solve_noalloc_max_bytes() bytes (64 MiB) that the library holds on
+ * every device it runs on until the process ends: solves whose
+ * rw_solve_workspace_bytes exceeds it return RW_ERR_WORKSPACE before any
+ * device work (e.g. float64 solves of up to about 2 million voxels with two
+ * labels, 1 million with three).  Every call on one device shares the array,
+ * so calls that overlap on one device (several contexts or threads) race.
+ * Launches are plain (opts->use_graph and kernel_timing are ignored); the
+ * context (rw_context_create) is the only set-up, and this call allocates no
+ * device or pinned memory.  Arguments and results otherwise as rw_solve. */
+size_t rw_solve_noalloc_max_bytes(void);
+rw_status rw_solve_noalloc(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
+                           const rw_options* opts, void* prob_out, uint8_t* argmax_out,
+                           rw_stats* stats, void* stream);
+
 /* One LOD step (levels of detail built by smoothing and downsampling, the
  * paper's Sec. III-D): g_out[c] = mean of the (up to) 2x2x2 fine values of g
  * in block c, g the normalised intensity of `fine` (pass a previous level's

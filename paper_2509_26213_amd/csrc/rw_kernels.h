@@ -23,6 +23,9 @@ rw_status ensure_events(rw_context* ctx, size_t n);
 // Grow the context's pinned host buffer / small device scratch (contents lost).
 rw_status ensure_host_pinned(rw_context* ctx, size_t bytes);
 rw_status ensure_dev_small(rw_context* ctx, size_t bytes);
+// Looks up the device address of the no-allocation solve's static scratch on
+// `device` (which must be current); once per device.
+rw_status noalloc_register_device(int device);
 
 // Tile shape of the stencil kernels, from the tuning table or the
 // environment.  Whole volumes: 64 vx columns (each lane owns vx of them, 64

@@ -38,7 +38,7 @@ EXPORTS = [
     "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
     "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_autotune_bricks",
-    "rw_argmax",
+    "rw_argmax", "rw_solve_noalloc", "rw_solve_noalloc_max_bytes",
 ]
 
 
@@ -141,6 +141,10 @@ def lib():
     L.rw_solve_workspace_bytes.restype = SZ
     L.rw_solve.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                            ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
+    L.rw_solve_noalloc.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
+                                   ctypes.POINTER(Options), P, P, ctypes.POINTER(Stats), P]
+    L.rw_solve_noalloc_max_bytes.argtypes = []
+    L.rw_solve_noalloc_max_bytes.restype = SZ
     L.rw_downsample.argtypes = [P, ctypes.POINTER(Volume), P, I32, P, P, P]
     L.rw_classify_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(I32),
                                      ctypes.POINTER(I32), D, D, ctypes.POINTER(Brick), P, I32,
@@ -355,6 +359,32 @@ def solve(vol, labels, K, beta, tol=1e-6, precision="fp64", lo=None, hi=None, ar
         d["status"] = status
         return out + (d,)
     return out
+
+
+def solve_noalloc(vol, labels, K, beta, prob_out, argmax_out=None, tol=1e-6, precision="fp64",
+                  lo=None, hi=None, ctx=None, return_stats=False, **kw):
+    """rw_solve_noalloc: the whole-volume solve with the library's static
+    device scratch instead of a workspace (the caller provides the outputs:
+    prob_out [K][grid], float64 for fp64, float32 for mixed; argmax_out uint8
+    [grid] or None).  Needs lo and hi, or a uint16 volume, to allocate
+    nothing here either."""
+    ctx = ctx or default_context()
+    V = make_volume(vol, lo, hi)
+    S = _seeds(labels, K)
+    o = options(beta, tol, precision, **kw)
+    st = Stats()
+    status = lib().rw_solve_noalloc(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
+                                    _ptr(prob_out), _ptr(argmax_out), ctypes.byref(st), _stream())
+    _check(status, "rw_solve_noalloc")
+    if return_stats:
+        d = st.to_dict()
+        d["status"] = status
+        return d
+    return status
+
+
+def solve_noalloc_max_bytes():
+    return int(lib().rw_solve_noalloc_max_bytes())
 
 
 def solve_workspace_bytes(shape, K, precision="fp64", solve_all_labels=False):
