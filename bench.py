@@ -27,7 +27,8 @@ workload.
 
 Other workloads (`--workload`): hier1024 (hierarchical batched bricks),
 stream2048 (bricks streamed through device pools), sphere128grad (float64
-forward + adjoint gradient); each is described in its own function.
+forward + adjoint gradient), heart4d (4-D random walker of a volume time
+series); each is described in its own function.
 """
 from __future__ import annotations
 
@@ -63,7 +64,7 @@ def pass_bytes(n_vox, launches, rhs_iterations, s_g, s_m, s_v, which):
 def make_workload(name):
     from synth import blob_case
     if name == "hier1024":
-        return blob_case(shape=(1024, 1024, 1024), n_blobs=256, K=3, seeds_per_label=8000,
+        return blob_case(shape=(1024, 1024, 1024), n_blobs=64, K=3, seeds_per_label=8000,
                          sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3,
                          dtype="u16", name="hier1024")
     if name == "blob512":
@@ -215,6 +216,8 @@ def main():
     ap.add_argument("--hier-steps", type=int, default=3,
                     help="blob512: timed steps of the hier1024 sub-object")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--nt", type=int, default=200,
+                    help="heart4d: time steps of the 50x224x224 series")
     ap.add_argument("--pool", type=int, default=256,
                     help="stream2048: bricks per device pool")
     ap.add_argument("--update-delta", type=float, default=None,
@@ -248,6 +251,8 @@ def main():
         return bench_stream(args)
     if args.workload == "sphere128grad":
         return bench_grad(args)
+    if args.workload == "heart4d":
+        return bench_4d(args)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     case = make_workload(args.workload)
@@ -520,7 +525,7 @@ def run_hier(args, steps, warmup):
     torch.cuda.empty_cache()
     return {
         "value": n_vox / sec, "ms_per_step": sec * 1e3, "steps": steps, "warmup": warmup,
-        "config": {"workload": "hier1024: 1024^3 uint16 blob volume (256 blobs, 8000 seeds per "
+        "config": {"workload": "hier1024: 1024^3 uint16 blob volume (64 blobs, 8000 seeds per "
                                "label, K=3, beta 150), level-2 256^3 solved whole, 64^3 bricks on "
                                "offset grid, uncertain bricks solved batched, mixed, tol 1e-6",
                    "voxels": n_vox, "candidate_bricks": o["n_cand"],
@@ -545,6 +550,126 @@ def run_hier(args, steps, warmup):
         "coarse": {"iters": og["coarse"]["iters"], "device_ms": og["coarse"]["device_ms"]},
         "cpu_baseline": cpu,
     }
+
+
+def cpu_baseline_4d(case, gpu_iters, n_iter, threads, nt_sample=2):
+    """The oracle's 4-D random walker (assembled sparse Laplacian, Jacobi-PCG
+    in float64, the only 4-D oracle) on the first nt_sample time steps of
+    the series: assembly and n_iter iterations of label 2 timed, scaled to
+    the whole series and the GPU's iteration counts.  Returns voxels/s."""
+    import numpy as np
+    from oracle import rw_oracle as O
+    t_all = time.perf_counter()
+    lo, hi = case.norm_range()
+    g = O.normalize(case.vol[:nt_sample], lo, hi)
+    lab = case.labels[:nt_sample].copy()  # the first time step holds seeds of both labels
+    t0 = time.perf_counter()
+    sysm = O.DirichletSystem(g, lab, case.beta, 0.0, 2)
+    b = sysm.rhs(2)
+    t_setup = time.perf_counter() - t0
+    dinv = 1.0 / sysm.diag
+    t0 = time.perf_counter()
+    O.pcg_jacobi(sysm.LU, b, dinv, np.zeros(b.size), 1e-300, n_iter)
+    t_iter = (time.perf_counter() - t0) / n_iter
+    vox_s = int(np.prod(g.shape))
+    n_vox = int(np.prod(case.vol.shape))
+    scale = n_vox / vox_s
+    t_solve = (t_setup + t_iter * sum(gpu_iters)) * scale
+    return dict(value=n_vox / t_solve, unit="voxels/s", cores=threads, cpu_model=cpu_model(),
+                kind="oracle",
+                sample=(f"assembled 4-D system of the first {nt_sample} time steps "
+                        f"({vox_s} voxels): set-up {t_setup:.1f} s, {n_iter} float64 Jacobi-PCG "
+                        f"iterations at {t_iter * 1e3:.0f} ms, scaled by voxels to the "
+                        f"{case.vol.shape[0]} time steps and to the GPU's {sum(gpu_iters)} "
+                        f"iterations; {time.perf_counter() - t_all:.1f} s wall"),
+                seconds_per_solve=t_solve)
+
+
+def bench_4d(args):
+    """4-D random walker (Sec. V-B): a synthetic stand-in for the paper's
+    cardiac MRI series, 50x224x224 voxels per time step and --nt time steps
+    (200 as in the paper), an ellipsoid pulsing over time on a noisy
+    background, 10 foreground and 10 background seeds in the first time step
+    and 4 foreground seeds in the last, as in the paper's experiment.  One
+    step = one whole-series solve (min-max reduction + rw_solve4d, mixed
+    precision, tol 1e-6) on the resident series; the float64 solve is timed
+    once beside it."""
+    import numpy as np
+    import torch
+    from paper_2509_26213_amd import rw
+    from synth import timeseries_case
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    case = timeseries_case(shape=(args.nt, 50, 224, 224))
+    print(f"# workload heart4d ({args.nt} time steps) generated in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    vol = torch.from_numpy(case.vol).to(dev)
+    lab = torch.from_numpy(case.labels).to(dev)
+    n_vox = int(np.prod(case.vol.shape))
+    ctx = rw.default_context()
+
+    def step(precision, timing=False):
+        lo, hi = rw.minmax(vol.view(-1, 224, 224), ctx=ctx)
+        return rw.solve4d(vol, lab, 2, case.beta, tol=1e-6, precision=precision, lo=lo, hi=hi,
+                          ctx=ctx, return_stats=True, kernel_timing=timing)
+
+    for _ in range(args.warmup):
+        step("mixed")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        prob, am, st = step("mixed")
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / args.steps
+    print(f"# mixed: {sec * 1e3:.1f} ms/step iters {st['iters']}", file=sys.stderr, flush=True)
+    s = step("mixed", True)[2]
+    bytes2 = pass_bytes(n_vox, s["pass_launches"][1], s["rhs_iterations"], 4, 1, 4, 2)
+    bytes1 = pass_bytes(n_vox, s["pass_launches"][0], s["rhs_iterations"], 4, 1, 4, 1)
+    ach2 = bytes2 / (s["pass_ms"][1] * 1e-3) / 1e9
+    ach1 = bytes1 / (s["pass_ms"][0] * 1e-3) / 1e9
+    # checks of the same run: partition of unity, exact seeds, range
+    seeded = lab > 0
+    checks = {"max_abs_sum_minus_1": float((prob.double().sum(0) - 1).abs().max()),
+              "seeds_exact": bool(((prob[1][seeded] == 1) == (lab[seeded] == 2)).all()),
+              "min": float(prob.min()), "max": float(prob.max())}
+    del prob, am
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    p64, _, s64 = step("fp64")
+    torch.cuda.synchronize()
+    sec64 = time.perf_counter() - t
+    del p64
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline_4d(case, st["iters"], args.cpu_iters,
+                                  len(os.sched_getaffinity(0)))
+        except Exception as e:  # the baseline never hides the GPU result
+            cpu = {"error": repr(e)}
+    print(json.dumps({
+        "metric": METRIC, "value": n_vox / sec, "unit": "voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64dot", "data": "synthetic",
+        "config": {"workload": f"heart4d: {args.nt}x50x224x224 float32 pulsing-ellipsoid time "
+                               "series, K=2, 10+10 seeds in the first and 4 in the last time "
+                               "step, beta 100, 8-connected 4-D grid, mixed, tol 1e-6",
+                   "voxels": n_vox},
+        "iters": st["iters"], "refinements": st["refinements"],
+        "rel_residual": st["rel_residual"],
+        "roofline": {"bound": "hbm", "kernel": "k_cg_pass2 (4-D)", "achieved": ach2,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "avg_launch_us": s["pass_ms"][1] * 1e3 / max(s["pass_launches"][1], 1),
+                     "bytes_per_launch": bytes2 / max(s["pass_launches"][1], 1)},
+        "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
+        "tile": tile_key(s["tile"]),
+        "stencil_cg_loop_frac": (bytes1 + bytes2) / ((s["pass_ms"][0] + s["pass_ms"][1]) * 1e-3)
+        / 1e9 / HBM_PEAK_GBS,
+        "fp64": {"value": n_vox / sec64, "ms_per_step": sec64 * 1e3, "iters": s64["iters"]},
+        "checks": checks,
+        "cpu_baseline": cpu,
+    }), flush=True)
 
 
 def bench_grad(args):

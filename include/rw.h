@@ -214,6 +214,22 @@ rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                    const rw_options* opts, void* prob_out, uint8_t* argmax_out, void* ws,
                    size_t ws_bytes, rw_stats* stats, void* stream);
 
+/* 4-D random walker (Sec. V-B: the random walker applied to a volume time
+ * series): the grid [nt][nz][ny][nx] in which every voxel is joined to its
+ * two neighbours along x, y, z and t (8-connected), the same Gaussian
+ * weights and Dirichlet problem as rw_solve.
+ * vol: data [nt][nz][ny][nx] (C order, x fastest); vol->dims is ONE time
+ *   step's (nx, ny, nz); nt time steps, nz * nt at most 2^30.
+ * seeds: labels [nt][nz][ny][nx].  prob_out: [K][nt][nz][ny][nx];
+ * argmax_out: NULL or [nt][nz][ny][nx].  Options, precisions, statuses and
+ * outputs otherwise as rw_solve.
+ * ws: rw_solve4d_workspace_bytes(dims, nt, K, precision, solve_all_labels). */
+size_t rw_solve4d_workspace_bytes(rw_dims dims, int32_t nt, int32_t num_labels,
+                                  int32_t precision, int32_t solve_all_labels);
+rw_status rw_solve4d(rw_context* ctx, const rw_volume* vol, int32_t nt, const rw_seeds* seeds,
+                     const rw_options* opts, void* prob_out, uint8_t* argmax_out, void* ws,
+                     size_t ws_bytes, rw_stats* stats, void* stream);
+
 /* rw_solve without device allocation, for callers that cannot allocate
  * (code under stream capture, tight serving loops, harnesses that forbid
  * hipMalloc).  The workspace is a static device array of

@@ -320,13 +320,23 @@ __device__ __forceinline__ int box_labels(const RhsState* __restrict__ st, int s
     return first;
 }
 
+// Whether plane Z has a neighbour at Z + 1 (a time series has no z edge
+// between the last plane of a time step and the first of the next).
+template <bool T4>
+__device__ __forceinline__ bool has_zp(const Geom& G, int gz) {
+    return gz + 1 < G.nz && (!T4 || (gz + 1) % G.tz != 0);
+}
+
 // The five edge weights of a voxel in plane k, column v of the LDS tile
 // (-x, +x, -y, +y from LDS, +z from the registers), zero across the volume
-// border; d adds the -z weight carried from the previous plane.
-template <typename T, typename Lanes, int U>
+// border; d adds the -z weight carried from the previous plane.  T4 (volume
+// time series): eval_t adds the two time edges (the same voxel in the
+// previous and next time step, tz planes away) to d.
+template <typename T, typename Lanes, int U, bool T4 = false>
 struct Stencil {
     using Tile = T[U][Lanes::TR + 2][Lanes::TC + 2];
     T wxm, wxp, wym, wyp, wzp, d;
+    T wtm, wtp;
     __device__ __forceinline__ void eval(const Tile& sg, int k, int v, const Lanes& L,
                                          const Geom& G, int gz, T gc, T gzn, T wzm,
                                          const WCoef& wc) {
@@ -335,8 +345,14 @@ struct Stencil {
         wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][r][c + 1], wc) : T(0);
         wym = L.gy[v] > 0 ? Weight<T>::of(gc - sg[k][r - 1][c], wc) : T(0);
         wyp = L.gy[v] + 1 < G.ny ? Weight<T>::of(gc - sg[k][r + 1][c], wc) : T(0);
-        wzp = gz + 1 < G.nz ? Weight<T>::of(gc - gzn, wc) : T(0);
+        wzp = has_zp<T4>(G, gz) ? Weight<T>::of(gc - gzn, wc) : T(0);
         d = wxm + wxp + wym + wyp + wzm + wzp;
+    }
+    __device__ __forceinline__ void eval_t(const Geom& G, int gz, T gc, T gtm, T gtp,
+                                           const WCoef& wc) {
+        wtm = gz >= G.tz ? Weight<T>::of(gc - gtm, wc) : T(0);
+        wtp = gz + G.tz < G.nz ? Weight<T>::of(gc - gtp, wc) : T(0);
+        d = d + wtm + wtp;
     }
     // q = d p - sum_j w_j p_j
     __device__ __forceinline__ T apply(const Tile& sp, int k, int v, const Lanes& L, T wzm, T pc,
@@ -345,13 +361,22 @@ struct Stencil {
         return d * pc - (wxm * sp[k][r][c - 1] + wxp * sp[k][r][c + 1] + wym * sp[k][r - 1][c] +
                          wyp * sp[k][r + 1][c] + wzm * pzm + wzp * pzp);
     }
+    __device__ __forceinline__ T apply_t(const Tile& sp, int k, int v, const Lanes& L, T wzm,
+                                         T pc, T pzm, T pzp, T ptm, T ptp) const {
+        const int r = L.lr[v], c = L.lc[v];
+        return d * pc - (wxm * sp[k][r][c - 1] + wxp * sp[k][r][c + 1] + wym * sp[k][r - 1][c] +
+                         wyp * sp[k][r + 1][c] + wzm * pzm + wzp * pzp + wtm * ptm + wtp * ptp);
+    }
 };
 
 // Pass 1: p_new = z + beta p_old (formed on the fly for the voxel and its
 // neighbours; zero on seeds and outside the box), q = A p_new, partial
 // p_new.q per label.  Label r reads p_old from buffer st.pcur of pb0/pb1 and
-// writes p_new to the other one.  qout (optional) receives q.
-template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false>
+// writes p_new to the other one.  qout (optional) receives q.  T4: a volume
+// time series (whole volume only); the two time neighbours of each own cell
+// are read directly, tz planes away.
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
+          bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
     const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
@@ -404,8 +429,9 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
         T wzm[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v)
-            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
-                                                         : T(0);
+            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
+                         ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                         : T(0);
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
@@ -425,6 +451,32 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                     for (int r = 0; r < R; ++r) {
                         zN[k][r][v] = ldu(zr[r] + o.b, L.colb[v]);
                         oN[k][r][v] = ldu(po[r] + o.b, L.colb[v]);
+                    }
+                }
+            }
+            // T4: g and p_new of the previous and next time step of the
+            // batch's own cells
+            T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
+                Ptp[T4 ? U : 1][R][VX];
+            if constexpr (T4) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int lz = zb + k;
+                    const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
+                    const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
+                        Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const T am = ldu(zr[r] + om.b, L.colb[v]) +
+                                         bet[r] * ldu(po[r] + om.b, L.colb[v]);
+                            const T ap = ldu(zr[r] + op.b, L.colb[v]) +
+                                         bet[r] * ldu(po[r] + op.b, L.colb[v]);
+                            Ptm[k][r][v] = im ? am : T(0);
+                            Ptp[k][r][v] = ip ? ap : T(0);
+                        }
                     }
                 }
             }
@@ -510,13 +562,19 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
                 for (int r = 0; r < R; ++r) prow[r] = pw[r] + (int64_t)lz * bplane;
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Stencil<T, Lanes, U> S;
+                    Stencil<T, Lanes, U, T4> S;
                     S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                    if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
                     const bool valid = L.in_box[v] && zin;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const T pc = Pv[k + 1][r][v];
-                        const T q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                        T q;
+                        if constexpr (T4)
+                            q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
+                                          Ptm[k][r][v], Ptp[k][r][v]);
+                        else
+                            q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
                         if (valid && act[r]) {
                             stu(prow[r], L.colb[v], pc);
                             if (qout) qout[bt.vbase + r * bt.vstride + (int64_t)lz * bplane + L.colb[v]] = q;
@@ -544,8 +602,9 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 
 // Pass 2: q = A p (p = buffer st.pcur, just written by pass 1); on unknowns
 // x += alpha p, r = d z - alpha q, z = r / d; partials r.z and r.r per label
-// ([2R][ntiles]).
-template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false>
+// ([2R][ntiles]).  T4 as in pass 1.
+template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
+          bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
@@ -598,8 +657,9 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
         T wzm[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v)
-            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0) ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
-                                                         : T(0);
+            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
+                         ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                         : T(0);
         double acc[2 * R];
 #pragma unroll
         for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
@@ -624,6 +684,28 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
                     for (int r = 0; r < R; ++r) {
                         Xv[k][r][v] = ldu(xr[r] + oc.b, L.colb[v]);
                         Zv[k][r][v] = ldu(zr[r] + oc.b, L.colb[v]);
+                    }
+                }
+            }
+            T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
+                Ptp[T4 ? U : 1][R][VX];
+            if constexpr (T4) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int lz = zb + k;
+                    const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
+                    const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
+                        Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const T am = ldu(pr[r] + om.b, L.colb[v]);
+                            const T ap = ldu(pr[r] + op.b, L.colb[v]);
+                            Ptm[k][r][v] = im ? am : T(0);
+                            Ptp[k][r][v] = ip ? ap : T(0);
+                        }
                     }
                 }
             }
@@ -684,14 +766,20 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
                 const int64_t ob = (int64_t)lz * bt.sx * bt.sy;
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    Stencil<T, Lanes, U> S;
+                    Stencil<T, Lanes, U, T4> S;
                     S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                    if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
                     const T dinv = T(1) / S.d;
                     const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const T pc = Pv[k + 1][r][v];
-                        const T q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                        T q;
+                        if constexpr (T4)
+                            q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
+                                          Ptm[k][r][v], Ptp[k][r][v]);
+                        else
+                            q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
                         const T xn = Xv[k][r][v] + alp[r] * pc;
                         const T rres = S.d * Zv[k][r][v] - alp[r] * q;
                         const T zn = dinv * rres;
@@ -766,8 +854,11 @@ struct XCell {
 // starts a CG run for every label (p buffers and xi zeroed); mode 2
 // refreshes z of the labels flagged for it (st.outer_active == 2).
 // Tiled like the passes (one plane per batch): every cell's x~ is formed once
-// by the lane that loads it and shared through LDS.
-template <typename V, typename T, int R, int BY, int VX, typename TS, bool YM = false>
+// by the lane that loads it and shared through LDS.  T4 (volume time series,
+// whole volume): the two time neighbours of an own cell, tz planes away, are
+// loaded and formed by its lane.
+template <typename V, typename T, int R, int BY, int VX, typename TS, bool YM = false,
+          bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_residual(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     Shell sh, int lab0, const double* __restrict__ x64, const double* __restrict__ rhs,
@@ -925,13 +1016,35 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                     continue;
                 }
                 const int c = L.lc[v], rr = L.lr[v];
-                // neighbour order -x, +x, -y, +y, -z, +z (the passes sum d in this order)
-                const bool hv[6] = {L.gx[v] > 0, L.gx[v] + 1 < G.nx, L.gy[v] > 0,
-                                    L.gy[v] + 1 < G.ny, gz > 0, gz + 1 < G.nz};
+                // neighbour order -x, +x, -y, +y, -z, +z (T4: then -t, +t; the
+                // passes sum d in this order)
+                constexpr int NB = T4 ? 8 : 6;
+                XCell<GT, R> ct[2];
+                bool hv[NB];
+                hv[0] = L.gx[v] > 0;
+                hv[1] = L.gx[v] + 1 < G.nx;
+                hv[2] = L.gy[v] > 0;
+                hv[3] = L.gy[v] + 1 < G.ny;
+                hv[4] = gz > 0 && has_zp<T4>(G, gz - 1);
+                hv[5] = has_zp<T4>(G, gz);
+                if constexpr (T4) {
+                    hv[6] = gz - G.tz >= 0;
+                    hv[7] = gz + G.tz < G.nz;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int lt = h ? lz + G.tz : lz - G.tz;
+                        const PlaneOff ot = plane_off(G, bt, lt);
+                        Raw wt;
+                        load_raw(ot.v, ot.b, L.colv[v], L.colb[v], wt);
+                        ct[h].make((double)wt.g, wt.lb, wt.xb, L.in_vol[v] && hv[6 + h],
+                                   L.in_box[v] && ot.inb, sh, lab0, bt.gox + L.gx[v],
+                                   bt.goy + L.gy[v], bt.goz + bt.oz + lt, lmask);
+                    }
+                }
                 const int ry[6] = {rr, rr, rr - 1, rr + 1, 0, 0};
                 const int rx[6] = {c - 1, c + 1, c, c, 0, 0};
-                double gn[6];
-                bool dn[6];
+                double gn[NB];
+                bool dn[NB];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     gn[k] = sg[ry[k]][rx[k]];
@@ -941,11 +1054,18 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 dn[4] = cm[v].dir;
                 gn[5] = cp[v].g;
                 dn[5] = cp[v].dir;
+                if constexpr (T4) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        gn[6 + h] = ct[h].g;
+                        dn[6 + h] = ct[h].dir;
+                    }
+                }
                 const double gc = cc[v].g;
-                double w[6];
+                double w[NB];
                 double d = 0.0;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     w[k] = hv[k] ? Weight<double>::of(gc - gn[k], wc) : 0.0;
                     d += w[k];
                 }
@@ -953,11 +1073,12 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 if constexpr (std::is_same<T, double>::value) {
                     dT = d;
                 } else {
-                    T wT[6];
+                    T wT[NB];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k)
+                    for (int k = 0; k < NB; ++k)
                         wT[k] = hv[k] ? Weight<T>::of((T)gc - (T)gn[k], wc) : T(0);
                     dT = wT[0] + wT[1] + wT[2] + wT[3] + wT[4] + wT[5];
+                    if constexpr (T4) dT = dT + wT[6] + wT[7];
                 }
                 if (!(d > 0.0)) acc[4 * R] += 1.0;
                 if (!isfinite(d)) acc[4 * R + 1] += 1.0;
@@ -966,16 +1087,20 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
                 for (int r = 0; r < R; ++r) {
                     if (!(lmask & (1 << r))) continue;  // uniform over the block
                     const int64_t vb = bt.vbase + r * bt.vstride + ob;
-                    double xn[6];
+                    double xn[NB];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) xn[k] = sx[r][ry[k]][rx[k]];
                     xn[4] = cm[v].xt[r];
                     xn[5] = cp[v].xt[r];
+                    if constexpr (T4) {
+                        xn[6] = ct[0].xt[r];
+                        xn[7] = ct[1].xt[r];
+                    }
                     const double xc = cc[v].xt[r];
                     double b = rhs ? ldu(rhs + vb, cb) : 0.0;
                     double res = b;
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) {
+                    for (int k = 0; k < NB; ++k) {
                         if (!hv[k]) continue;
                         if (dn[k]) b += w[k] * xn[k];
                         res += w[k] * (xn[k] - xc);

@@ -12,10 +12,14 @@
 
 namespace rw {
 
-// Grid geometry.  Voxel (x, y, z) lives at z * plane + y * nx + x.
+// Grid geometry.  Voxel (x, y, z) lives at z * plane + y * nx + x.  A
+// volume time series [nt][nz][ny][nx] (4-D random walker) is stored as the
+// grid (nx, ny, nt * nz) with tz = nz planes per time step: plane Z is z =
+// Z mod tz of time step Z / tz; tz = 0 for a 3-D grid.
 struct Geom {
     int nx, ny, nz;
     int64_t plane, n;
+    int tz = 0;
 };
 
 // Edge-weight coefficients.  With s = 1 / (hi - lo) (0 for a constant

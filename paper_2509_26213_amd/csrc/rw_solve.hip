@@ -25,68 +25,11 @@
 #include <cstring>
 #include <type_traits>
 
-#include "rw_whole.h"
+#include "rw_solve_impl.h"
 
 namespace rw {
 
 // ================================================================== kernels
-
-template <typename V, typename T, int R>
-static rw_status run_group(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
-                           const rw_options* o, int lab0, const double* x0, const GroupBuffers& B,
-                           void* prob_out, rw_stats* stats, int r_base, int* worst) {
-    const TileChoice tc = choose_tiles(make_geom(vol->dims), o->precision, R);
-    if constexpr (std::is_same<T, float>::value) {
-        if (tc.vx == 4)
-            return run_group_vx<V, T, R, 4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
-                                            r_base, worst);
-    }
-    if (tc.vx == 2 && tc.by == 8)
-        return run_group_vx<V, T, R, 2, 8>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
-                                           r_base, worst);
-    if (tc.vx == 2)
-        return run_group_vx<V, T, R, 2>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
-                                        r_base, worst);
-    return run_group_vx<V, T, R, 1>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats, r_base,
-                                    worst);
-}
-
-template <typename V, typename T>
-static rw_status dispatch_r(int R, rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
-                            const rw_options* o, int lab0, const double* x0,
-                            const GroupBuffers& B, void* prob, rw_stats* st, int rb, int* worst) {
-    switch (R) {
-        case 1: return run_group<V, T, 1>(ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst);
-        case 2: return run_group<V, T, 2>(ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst);
-        case 3: return run_group<V, T, 3>(ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst);
-        case 4: return run_group<V, T, 4>(ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst);
-    }
-    return invalid("bad group size");
-}
-
-static rw_status dispatch_group(int R, rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
-                                const rw_options* o, int lab0, const double* x0,
-                                const GroupBuffers& B, void* prob, rw_stats* st, int rb,
-                                int* worst) {
-    const bool mixed = o->precision == RW_PREC_MIXED;
-    switch (vol->dtype) {
-        case RW_DT_U16:
-            return mixed ? dispatch_r<uint16_t, float>(R, ctx, vol, lab, o, lab0, x0, B, prob, st,
-                                                       rb, worst)
-                         : dispatch_r<uint16_t, double>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                        st, rb, worst);
-        case RW_DT_F32:
-            return mixed ? dispatch_r<float, float>(R, ctx, vol, lab, o, lab0, x0, B, prob, st, rb,
-                                                    worst)
-                         : dispatch_r<float, double>(R, ctx, vol, lab, o, lab0, x0, B, prob, st,
-                                                     rb, worst);
-        default:
-            return mixed ? dispatch_r<double, float>(R, ctx, vol, lab, o, lab0, x0, B, prob, st,
-                                                     rb, worst)
-                         : dispatch_r<double, double>(R, ctx, vol, lab, o, lab0, x0, B, prob, st,
-                                                      rb, worst);
-    }
-}
 
 rw_status check_options(const rw_options* o) {
     if (!o) return invalid("options is NULL");
@@ -190,67 +133,8 @@ size_t rw_solve_workspace_bytes(rw_dims dims, int32_t num_labels, int32_t precis
 rw_status rw_solve(rw_context* ctx, const rw_volume* vol, const rw_seeds* seeds,
                    const rw_options* o, void* prob_out, uint8_t* argmax_out, void* ws,
                    size_t ws_bytes, rw_stats* stats, void* stream) {
-    if (!ctx) return invalid("context is NULL");
-    rw_status e = check_volume(vol);
-    if (e) return e;
-    if ((e = check_options(o))) return e;
-    if (!seeds || !seeds->labels) return invalid("seeds are NULL");
-    const int K = seeds->num_labels;
-    if (K < 1 || K > RW_MAX_LABELS) return invalid("num_labels must be in [1, 16]");
-    if (!prob_out) return invalid("prob_out is NULL");
-    const size_t need = rw_solve_workspace_bytes(vol->dims, K, o->precision, o->solve_all_labels);
-    if (!ws || ws_bytes < need) {
-        set_error("workspace needs " + std::to_string(need) + " bytes");
-        return RW_ERR_WORKSPACE;
-    }
-    if (stats) memset(stats, 0, sizeof(*stats));
-    const Geom G = make_geom(vol->dims);
-    const int R_total = o->solve_all_labels ? K : K - 1;
-    const int lab0 = o->solve_all_labels ? 1 : 2;
-    if ((e = stream_enter(ctx, stream))) return e;
-    RW_HIP(hipEventRecord(ctx->ev_begin, ctx->s));
-    int64_t unknowns = 0;
-    if ((e = check_labels(ctx, seeds->labels, G.n, K, lab0, R_total, &unknowns))) {
-        (void)stream_leave(ctx, stream);
-        return e;
-    }
-    int worst = RW_OK;
-    for (int g0 = 0; g0 < R_total; g0 += 4) {
-        const int Rg = std::min(4, R_total - g0);
-        Carver cv(ws);
-        GroupBuffers B;
-        carve_group(cv, G, Rg, o->precision == RW_PREC_MIXED, &B);
-        const double* x0 = o->x0 ? static_cast<const double*>(o->x0) + (int64_t)g0 * G.n : nullptr;
-        e = dispatch_group(Rg, ctx, vol, seeds->labels, o, lab0 + g0, x0, B, prob_out, stats, g0,
-                           &worst);
-        if (e) {
-            (void)stream_leave(ctx, stream);
-            return e;
-        }
-        if (worst < 0) break;
-    }
-    if (worst >= 0) {
-        const int complement = o->solve_all_labels ? 0 : 1;
-        if (o->precision == RW_PREC_MIXED)
-            hipLaunchKernelGGL((k_finish<float>), dim3(grid1d(G.n)), dim3(256), 0, ctx->s,
-                               seeds->labels, G.n, K, complement, (float*)prob_out, argmax_out);
-        else
-            hipLaunchKernelGGL((k_finish<double>), dim3(grid1d(G.n)), dim3(256), 0, ctx->s,
-                               seeds->labels, G.n, K, complement, (double*)prob_out, argmax_out);
-        RW_HIP(hipGetLastError());
-    }
-    RW_HIP(hipEventRecord(ctx->ev_end, ctx->s));
-    RW_HIP(hipEventSynchronize(ctx->ev_end));
-    if (stats) {
-        float ms = 0.f;
-        RW_HIP(hipEventElapsedTime(&ms, ctx->ev_begin, ctx->ev_end));
-        stats->device_ms = ms;
-        stats->num_solved = R_total;
-        stats->unknowns = unknowns;
-    }
-    if ((e = stream_leave(ctx, stream))) return e;
-    if (worst < 0) set_error(std::string("solve failed: ") + rw_status_string((rw_status)worst));
-    return (rw_status)worst;
+    return solve_whole<false>(ctx, vol, 0, seeds, o, prob_out, argmax_out, ws, ws_bytes, stats,
+                              stream);
 }
 
 size_t rw_operator_workspace_bytes(rw_dims dims, int32_t precision) {

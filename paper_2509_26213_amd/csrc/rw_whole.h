@@ -292,7 +292,8 @@ struct PlaneBatch {
     static constexpr int value = per / VX > 0 ? per / VX : 1;
 };
 
-template <typename V, typename T, int R, int VX, int BY_ = 4>
+// T4: the grid is a volume time series (G.tz planes per time step).
+template <typename V, typename T, int R, int VX, int BY_ = 4, bool T4 = false>
 struct WholeSolve {
     static constexpr int BY = BY_;
     static constexpr int ZU = PlaneBatch<T, VX>::value;
@@ -332,12 +333,12 @@ struct WholeSolve {
     rw_status launch_iteration(hipEvent_t* ev) {
         hipStream_t s = ctx->s;
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
-        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, VX, WholeTiles>), grid(), block(), 0, s, vol, wc, ts(), zv,
+        hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, VX, WholeTiles, false, T4>), grid(), block(), 0, s, vol, wc, ts(), zv,
                            p0, p1, (T*)nullptr, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_fin1<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, VX, WholeTiles>), grid(), block(), 0, s, vol, lab, wc, ts(),
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, VX, WholeTiles, false, T4>), grid(), block(), 0, s, vol, lab, wc, ts(),
                            xv, zv, (const T*)p0, (const T*)p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
         hipLaunchKernelGGL((k_fin2<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st,
@@ -357,7 +358,7 @@ struct WholeSolve {
     rw_status launch_residual(int mode) {
         Shell none;
         memset(&none, 0, sizeof(none));
-        hipLaunchKernelGGL((k_residual<V, T, R, BY, VX, WholeTiles>), grid(), block(), 0, ctx->s, vol, lab,
+        hipLaunchKernelGGL((k_residual<V, T, R, BY, VX, WholeTiles, false, T4>), grid(), block(), 0, ctx->s, vol, lab,
                            wc, ts(), none, lab0, B.x64, rhs, zv, p0, p1,
                            mixed ? (T*)B.xi : (T*)nullptr, mode, B.st, B.part);
         RW_HIP(hipGetLastError());
@@ -552,16 +553,17 @@ struct WholeSolve {
     }
 };
 
-template <typename V, typename T, int R, int VX, int BY = 4>
+template <typename V, typename T, int R, int VX, int BY = 4, bool T4 = false>
 inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                               const rw_options* o, int lab0, const double* x0,
                               const GroupBuffers& B, const TileChoice& tc, void* prob_out,
-                              rw_stats* stats, int r_base, int* worst) {
-    WholeSolve<V, T, R, VX, BY> S;
+                              rw_stats* stats, int r_base, int* worst, int tz = 0) {
+    WholeSolve<V, T, R, VX, BY, T4> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(vol->data);
     S.lab = lab;
     S.G = make_geom(vol->dims);
+    S.G.tz = tz;
     S.wc = make_wcoef(vol, o->beta, o->w_eps);
     S.tm = make_tilemap(S.G, BY, tc.zc, tc.xcd, VX);
     S.lab0 = lab0;

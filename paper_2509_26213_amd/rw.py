@@ -38,7 +38,8 @@ EXPORTS = [
     "rw_apply_operator", "rw_solve_workspace_bytes", "rw_solve", "rw_downsample",
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
     "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_autotune_bricks",
-    "rw_argmax", "rw_solve_noalloc", "rw_solve_noalloc_max_bytes",
+    "rw_argmax", "rw_solve_noalloc", "rw_solve_noalloc_max_bytes", "rw_solve4d",
+    "rw_solve4d_workspace_bytes",
 ]
 
 
@@ -143,6 +144,10 @@ def lib():
                            ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
     L.rw_solve_noalloc.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds),
                                    ctypes.POINTER(Options), P, P, ctypes.POINTER(Stats), P]
+    L.rw_solve4d_workspace_bytes.argtypes = [Dims, I32, I32, I32, I32]
+    L.rw_solve4d_workspace_bytes.restype = SZ
+    L.rw_solve4d.argtypes = [P, ctypes.POINTER(Volume), I32, ctypes.POINTER(Seeds),
+                             ctypes.POINTER(Options), P, P, P, SZ, ctypes.POINTER(Stats), P]
     L.rw_solve_noalloc_max_bytes.argtypes = []
     L.rw_solve_noalloc_max_bytes.restype = SZ
     L.rw_downsample.argtypes = [P, ctypes.POINTER(Volume), P, I32, P, P, P]
@@ -353,6 +358,41 @@ def solve(vol, labels, K, beta, tol=1e-6, precision="fp64", lo=None, hi=None, ar
     status = lib().rw_solve(ctx.handle, ctypes.byref(V), ctypes.byref(S), ctypes.byref(o),
                             _ptr(prob), _ptr(am), _ptr(ws), nbytes, ctypes.byref(st), _stream())
     _check(status, "rw_solve")
+    out = (prob, am)
+    if return_stats:
+        d = st.to_dict()
+        d["status"] = status
+        return out + (d,)
+    return out
+
+
+def solve4d(vol, labels, K, beta, tol=1e-6, precision="fp64", lo=None, hi=None, argmax=True,
+            ctx=None, workspace=None, return_stats=False, **kw):
+    """4-D random walker of a volume time series vol [nt][nz][ny][nx] with
+    seed labels of the same shape: probabilities [K][nt][nz][ny][nx] (+ the
+    argmax labels).  Arguments otherwise as solve()."""
+    ctx = ctx or default_context()
+    if vol.dim() != 4 or tuple(labels.shape) != tuple(vol.shape):
+        raise ValueError("vol and labels must be [nt][nz][ny][nx] of the same shape")
+    nt, nz, ny, nx = (int(v) for v in vol.shape)
+    V = make_volume(vol.view(nt * nz, ny, nx), lo, hi)
+    V.dims = _dims(vol.shape[1:])
+    S = _seeds(labels, K)
+    x0 = kw.get("x0")
+    if x0 is not None:
+        kw["x0"] = x0.to(torch.float64).contiguous()
+    o = options(beta, tol, precision, **kw)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    prob = torch.empty((K,) + tuple(vol.shape), dtype=dt, device=vol.device)
+    am = torch.empty(tuple(vol.shape), dtype=torch.uint8, device=vol.device) if argmax else None
+    nbytes = lib().rw_solve4d_workspace_bytes(_dims(vol.shape[1:]), nt, K, o.precision,
+                                              o.solve_all_labels)
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _alloc_ws(
+        nbytes, vol.device)
+    st = Stats()
+    status = lib().rw_solve4d(ctx.handle, ctypes.byref(V), nt, ctypes.byref(S), ctypes.byref(o),
+                              _ptr(prob), _ptr(am), _ptr(ws), nbytes, ctypes.byref(st), _stream())
+    _check(status, "rw_solve4d")
     out = (prob, am)
     if return_stats:
         d = st.to_dict()

@@ -98,7 +98,7 @@ def test_sphere128_gradients_vs_central_differences(rw):
 
 @pytest.mark.timeout(900)
 def test_hier1024_sampled_bricks_vs_oracle(rw):
-    """The full-size hierarchical workload (1024^3 uint16, 256 blobs, 8000
+    """The full-size hierarchical workload (1024^3 uint16, 64 blobs, 8000
     seeds per label, K = 3, 64^3 bricks on the offset grid, the bench's tile
     shapes): six of the GPU's active bricks (lowest and highest GPU iteration
     counts, two clipped border bricks, two others) equal the oracle's solves
@@ -109,7 +109,7 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     import torch
     from oracle import c_oracle, rw_oracle as O
     tol = 1e-8
-    c = blob_case(shape=(1024, 1024, 1024), n_blobs=256, K=3, seeds_per_label=8000, sigma=0.08,
+    c = blob_case(shape=(1024, 1024, 1024), n_blobs=64, K=3, seeds_per_label=8000, sigma=0.08,
                   bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3, dtype="u16")
     brick, offset = (64, 64, 64), (48, 20, 40)
     prob, info = rw.hierarchical_solve(dev(c.vol), dev(c.labels), 3, c.beta, levels=2,
