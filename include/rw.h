@@ -139,6 +139,8 @@ typedef struct {
     int64_t unknowns;                    /* unseeded voxels solved for */
     int32_t tile_vx;                     /* columns per lane (1, 2, 4) */
     int32_t tile_xcd;                    /* 1: XCD-aware tile order */
+    int32_t brick_blocks;                /* brick solves: blocks of the one persistent
+                                            launch (0: one launch per CG pass) */
 } rw_stats;
 
 /* Fine-level brick: origin and size in voxels of the fine grid (or of its

@@ -1,0 +1,12 @@
+// Batched brick solves for uint16_t volumes in mixed precision (float32 CG).
+#include "rw_bricks.h"
+
+namespace rw {
+
+rw_status bricks_u16_f32(int R, rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
+                        const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
+                        const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
+    return bricks_r<uint16_t, float>(R, ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws, st);
+}
+
+}  // namespace rw

@@ -117,8 +117,14 @@ struct BrickTiles {
         }
         const int g = list[i];
         const int bi = tile_brick[g];
-        const BrickGeo B = bricks[bi];
-        const int t = g - B.tile0;
+        brick_tile(bricks[bi], g - bricks[bi].tile0, zc, by, bi, g, b);
+        return true;
+    }
+
+    // Tile t of brick B (tiles of 64 x by columns by zc planes, x fastest,
+    // then y, then z); its RhsState rows are sidx * R.., its partial slot pidx.
+    static __device__ __forceinline__ void brick_tile(const BrickGeo& B, int t, int zc, int by,
+                                                      int sidx, int pidx, BoxTile& b) {
         const int tx = t % B.gx, ty = (t / B.gx) % B.gy, tz = t / (B.gx * B.gy);
         b.G.nx = B.vnx;
         b.G.ny = B.vny;
@@ -142,9 +148,8 @@ struct BrickTiles {
         b.z1 = min(b.z0 + zc, B.sz);
         b.vbase = B.voff;
         b.vstride = B.vox;
-        b.sidx = bi;
-        b.pidx = g;
-        return true;
+        b.sidx = sidx;
+        b.pidx = pidx;
     }
 };
 
@@ -375,227 +380,252 @@ struct Stencil {
 // writes p_new to the other one.  qout (optional) receives q.  T4: a volume
 // time series (whole volume only); the two time neighbours of each own cell
 // are read directly, tz planes away.
+template <typename T, int R, int BY, int U, int VX, bool YM>
+struct PassSmem {
+    using Lanes = TileLanes<BY, U, VX, YM>;
+    static constexpr size_t plane = size_t(U) * (Lanes::TR + 2) * (Lanes::TC + 2);
+    static constexpr size_t bytes = sizeof(T) * plane * (1 + R);
+};
+
+// One tile of pass 1, accumulated into acc (per label p_new.q); false if no
+// label of the tile's box iterates (uniform over the block).  smem: at least
+// PassSmem<T, R, BY, U, VX, YM>::bytes of LDS.
+template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false>
+__device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const BoxTile& bt,
+                                              const V* __restrict__ volp, WCoef wc,
+                                              const T* __restrict__ zv, T* __restrict__ pb0,
+                                              T* __restrict__ pb1, T* __restrict__ qout,
+                                              const RhsState* __restrict__ st,
+                                              double (&acc)[R]) {
+    using Lanes = TileLanes<BY, U, VX, YM>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int HV = Lanes::HV;
+    using Plane = T[U][Lanes::TR + 2][Lanes::TC + 2];
+    Plane& sg = *reinterpret_cast<Plane*>(smem);
+    Plane(&sp)[R] = *reinterpret_cast<Plane(*)[R]>(smem + sizeof(Plane));
+    bool act[R];
+    int src[R];
+    if (box_labels<R>(st, bt.sidx, act, src) < 0) return false;  // uniform over the block
+    const Geom& G = bt.G;
+    const V* __restrict__ vol = volp + bt.voff;
+    T bet[R];
+    const T* zr[R];
+    const T* po[R];
+    T* pw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const RhsState& s = st[bt.sidx * R + src[r]];
+        bet[r] = (T)s.beta;
+        zr[r] = zv + bt.vbase + src[r] * bt.vstride;
+        po[r] = (s.pcur ? pb1 : pb0) + bt.vbase + src[r] * bt.vstride;
+        pw[r] = (st[bt.sidx * R + r].pcur ? pb0 : pb1) + bt.vbase + r * bt.vstride;
+    }
+    Lanes L;
+    L.init(G, bt);
+    const int64_t bplane = (int64_t)bt.sx * bt.sy;
+
+    T Gv[U + 2][VX], Pv[U + 2][R][VX];  // own columns: planes z-1, z, z+1 .. z+U
+    {
+        const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
+            Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T a = ldu(zr[r] + om.b, L.colb[v]) + bet[r] * ldu(po[r] + om.b, L.colb[v]);
+                Pv[0][r][v] = om.inb ? a : T(0);
+                Pv[1][r][v] = ldu(zr[r] + oc.b, L.colb[v]) + bet[r] * ldu(po[r] + oc.b, L.colb[v]);
+            }
+        }
+    }
+    T wzm[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v)
+        wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
+                     ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                     : T(0);
+
+    for (int zb = bt.z0; zb < bt.z1; zb += U) {
+        // (1) every read of the batch
+        T zN[U][R][VX], oN[U][R][VX];
+        bool nin[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const PlaneOff o = plane_off(G, bt, zb + 1 + k);
+            nin[k] = o.inb;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    zN[k][r][v] = ldu(zr[r] + o.b, L.colb[v]);
+                    oN[k][r][v] = ldu(po[r] + o.b, L.colb[v]);
+                }
+            }
+        }
+        // T4: g and p_new of the previous and next time step of the
+        // batch's own cells
+        T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
+            Ptp[T4 ? U : 1][R][VX];
+        if constexpr (T4) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int lz = zb + k;
+                const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
+                const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
+                    Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T am = ldu(zr[r] + om.b, L.colb[v]) +
+                                     bet[r] * ldu(po[r] + om.b, L.colb[v]);
+                        const T ap = ldu(zr[r] + op.b, L.colb[v]) +
+                                     bet[r] * ldu(po[r] + op.b, L.colb[v]);
+                        Ptm[k][r][v] = im ? am : T(0);
+                        Ptp[k][r][v] = ip ? ap : T(0);
+                    }
+                }
+            }
+        }
+        T hxg, hxz[R], hxo[R];
+        {
+            const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
+            hxg = (T)ldu(vol + o.v, L.hx_colv);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                hxz[r] = ldu(zr[r] + o.b, L.hx_colb);
+                hxo[r] = ldu(po[r] + o.b, L.hx_colb);
+            }
+        }
+        T hyg[NYH][HV], hyz[NYH][R][HV], hyo[NYH][R][HV];
+#pragma unroll
+        for (int j = 0; j < NYH; ++j) {
+            const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
+#pragma unroll
+            for (int h = 0; h < HV; ++h) {
+                hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    hyz[j][r][h] = ldu(zr[r] + o.b, L.hy_colb[j][h]);
+                    hyo[j][r][h] = ldu(po[r] + o.b, L.hy_colb[j][h]);
+                }
+            }
+        }
+        // (2) the previous batch (or tile) is done with the LDS planes
+        __syncthreads();
+        // (3) publish planes zb..zb+U-1
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                if (k > 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        Pv[k + 1][r][v] =
+                            nin[k - 1] ? zN[k - 1][r][v] + bet[r] * oN[k - 1][r][v] : T(0);
+                }
+                sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
+            }
+        }
+        if (L.hx_use) {
+            sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] =
+                    L.hx_box ? hxz[r] + bet[r] * hxo[r] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NYH; ++j) {
+            if (L.hy_use[j]) {
+#pragma unroll
+                for (int h = 0; h < HV; ++h) {
+                    const int c = 64 * h + L.lx + 1;
+                    sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
+                            L.hy_box[j][h] ? hyz[j][r][h] + bet[r] * hyo[j][r][h] : T(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VX; ++v)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                Pv[U + 1][r][v] =
+                    nin[U - 1] ? zN[U - 1][r][v] + bet[r] * oN[U - 1][r][v] : T(0);
+        __syncthreads();
+        // (4) stencil on planes zb..zb+U-1
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int lz = zb + k;
+            const int gz = bt.oz + lz;
+            const bool zin = lz < bt.z1;
+            T* __restrict__ prow[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) prow[r] = pw[r] + (int64_t)lz * bplane;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Stencil<T, Lanes, U, T4> S;
+                S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
+                const bool valid = L.in_box[v] && zin;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T pc = Pv[k + 1][r][v];
+                    T q;
+                    if constexpr (T4)
+                        q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
+                                      Ptm[k][r][v], Ptp[k][r][v]);
+                    else
+                        q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                    if (valid && act[r]) {
+                        stu(prow[r], L.colb[v], pc);
+                        if (qout) qout[bt.vbase + r * bt.vstride + (int64_t)lz * bplane + L.colb[v]] = q;
+                        acc[r] += (double)pc * (double)q;
+                    }
+                }
+                wzm[v] = S.wzp;
+            }
+        }
+        // (5) carry planes zb+U-1 and zb+U
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            Gv[0][v] = Gv[U][v];
+            Gv[1][v] = Gv[U + 1][v];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Pv[0][r][v] = Pv[U][r][v];
+                Pv[1][r][v] = Pv[U + 1][r][v];
+            }
+        }
+    }
+    return true;
+}
+
 template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
           bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
     const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
     const RhsState* __restrict__ st, double* __restrict__ part) {
-    using Lanes = TileLanes<BY, U, VX, YM>;
-    constexpr int NYH = Lanes::NYH;
-    constexpr int HV = Lanes::HV;
-    __shared__ T sg[U][Lanes::TR + 2][Lanes::TC + 2];
-    __shared__ T sp[R][U][Lanes::TR + 2][Lanes::TC + 2];
+    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
         if (!ts.get(it, bt)) continue;
-        bool act[R];
-        int src[R];
-        if (box_labels<R>(st, bt.sidx, act, src) < 0) continue;  // uniform over the block
-        const Geom& G = bt.G;
-        const V* __restrict__ vol = volp + bt.voff;
-        T bet[R];
-        const T* zr[R];
-        const T* po[R];
-        T* pw[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const RhsState& s = st[bt.sidx * R + src[r]];
-            bet[r] = (T)s.beta;
-            zr[r] = zv + bt.vbase + src[r] * bt.vstride;
-            po[r] = (s.pcur ? pb1 : pb0) + bt.vbase + src[r] * bt.vstride;
-            pw[r] = (st[bt.sidx * R + r].pcur ? pb0 : pb1) + bt.vbase + r * bt.vstride;
-        }
-        Lanes L;
-        L.init(G, bt);
-        const int64_t bplane = (int64_t)bt.sx * bt.sy;
-
-        T Gv[U + 2][VX], Pv[U + 2][R][VX];  // own columns: planes z-1, z, z+1 .. z+U
-        {
-            const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
-                Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T a = ldu(zr[r] + om.b, L.colb[v]) + bet[r] * ldu(po[r] + om.b, L.colb[v]);
-                    Pv[0][r][v] = om.inb ? a : T(0);
-                    Pv[1][r][v] = ldu(zr[r] + oc.b, L.colb[v]) + bet[r] * ldu(po[r] + oc.b, L.colb[v]);
-                }
-            }
-        }
-        T wzm[VX];
-#pragma unroll
-        for (int v = 0; v < VX; ++v)
-            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
-                         ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
-                         : T(0);
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
-
-        for (int zb = bt.z0; zb < bt.z1; zb += U) {
-            // (1) every read of the batch
-            T zN[U][R][VX], oN[U][R][VX];
-            bool nin[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const PlaneOff o = plane_off(G, bt, zb + 1 + k);
-                nin[k] = o.inb;
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        zN[k][r][v] = ldu(zr[r] + o.b, L.colb[v]);
-                        oN[k][r][v] = ldu(po[r] + o.b, L.colb[v]);
-                    }
-                }
-            }
-            // T4: g and p_new of the previous and next time step of the
-            // batch's own cells
-            T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
-                Ptp[T4 ? U : 1][R][VX];
-            if constexpr (T4) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int lz = zb + k;
-                    const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
-                    const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
-                        Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const T am = ldu(zr[r] + om.b, L.colb[v]) +
-                                         bet[r] * ldu(po[r] + om.b, L.colb[v]);
-                            const T ap = ldu(zr[r] + op.b, L.colb[v]) +
-                                         bet[r] * ldu(po[r] + op.b, L.colb[v]);
-                            Ptm[k][r][v] = im ? am : T(0);
-                            Ptp[k][r][v] = ip ? ap : T(0);
-                        }
-                    }
-                }
-            }
-            T hxg, hxz[R], hxo[R];
-            {
-                const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)ldu(vol + o.v, L.hx_colv);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    hxz[r] = ldu(zr[r] + o.b, L.hx_colb);
-                    hxo[r] = ldu(po[r] + o.b, L.hx_colb);
-                }
-            }
-            T hyg[NYH][HV], hyz[NYH][R][HV], hyo[NYH][R][HV];
-#pragma unroll
-            for (int j = 0; j < NYH; ++j) {
-                const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
-#pragma unroll
-                for (int h = 0; h < HV; ++h) {
-                    hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        hyz[j][r][h] = ldu(zr[r] + o.b, L.hy_colb[j][h]);
-                        hyo[j][r][h] = ldu(po[r] + o.b, L.hy_colb[j][h]);
-                    }
-                }
-            }
-            // (2) the previous batch (or tile) is done with the LDS planes
-            __syncthreads();
-            // (3) publish planes zb..zb+U-1
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    if (k > 0) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            Pv[k + 1][r][v] =
-                                nin[k - 1] ? zN[k - 1][r][v] + bet[r] * oN[k - 1][r][v] : T(0);
-                    }
-                    sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
-                }
-            }
-            if (L.hx_use) {
-                sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] =
-                        L.hx_box ? hxz[r] + bet[r] * hxo[r] : T(0);
-            }
-#pragma unroll
-            for (int j = 0; j < NYH; ++j) {
-                if (L.hy_use[j]) {
-#pragma unroll
-                    for (int h = 0; h < HV; ++h) {
-                        const int c = 64 * h + L.lx + 1;
-                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
-                                L.hy_box[j][h] ? hyz[j][r][h] + bet[r] * hyo[j][r][h] : T(0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < VX; ++v)
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    Pv[U + 1][r][v] =
-                        nin[U - 1] ? zN[U - 1][r][v] + bet[r] * oN[U - 1][r][v] : T(0);
-            __syncthreads();
-            // (4) stencil on planes zb..zb+U-1
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int lz = zb + k;
-                const int gz = bt.oz + lz;
-                const bool zin = lz < bt.z1;
-                T* __restrict__ prow[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) prow[r] = pw[r] + (int64_t)lz * bplane;
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    Stencil<T, Lanes, U, T4> S;
-                    S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
-                    if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
-                    const bool valid = L.in_box[v] && zin;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const T pc = Pv[k + 1][r][v];
-                        T q;
-                        if constexpr (T4)
-                            q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
-                                          Ptm[k][r][v], Ptp[k][r][v]);
-                        else
-                            q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
-                        if (valid && act[r]) {
-                            stu(prow[r], L.colb[v], pc);
-                            if (qout) qout[bt.vbase + r * bt.vstride + (int64_t)lz * bplane + L.colb[v]] = q;
-                            acc[r] += (double)pc * (double)q;
-                        }
-                    }
-                    wzm[v] = S.wzp;
-                }
-            }
-            // (5) carry planes zb+U-1 and zb+U
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = Gv[U][v];
-                Gv[1][v] = Gv[U + 1][v];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    Pv[0][r][v] = Pv[U][r][v];
-                    Pv[1][r][v] = Pv[U + 1][r][v];
-                }
-            }
-        }
+        if (!cg_pass1_tile<V, T, R, BY, U, VX, YM, T4>(smem, bt, volp, wc, zv, pb0, pb1, qout, st,
+                                                       acc))
+            continue;
         block_sum_store<R, BY>(acc, part + bt.pidx, ts.ntiles);
     }
 }
@@ -603,209 +633,227 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 // Pass 2: q = A p (p = buffer st.pcur, just written by pass 1); on unknowns
 // x += alpha p, r = d z - alpha q, z = r / d; partials r.z and r.r per label
 // ([2R][ntiles]).  T4 as in pass 1.
+// One tile of pass 2, accumulated into acc (per label r.z, r.r); false if
+// no label of the tile's box iterates.  smem as for pass 1.
+template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false>
+__device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const BoxTile& bt,
+                                              const V* __restrict__ volp,
+                                              const uint8_t* __restrict__ labp, WCoef wc,
+                                              T* __restrict__ xv, T* __restrict__ zv,
+                                              const T* __restrict__ pb0, const T* __restrict__ pb1,
+                                              const RhsState* __restrict__ st,
+                                              double (&acc)[2 * R]) {
+    using Lanes = TileLanes<BY, U, VX, YM>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int HV = Lanes::HV;
+    using Plane = T[U][Lanes::TR + 2][Lanes::TC + 2];
+    Plane& sg = *reinterpret_cast<Plane*>(smem);
+    Plane(&sp)[R] = *reinterpret_cast<Plane(*)[R]>(smem + sizeof(Plane));
+    bool act[R];
+    int src[R];
+    if (box_labels<R>(st, bt.sidx, act, src) < 0) return false;
+    const Geom& G = bt.G;
+    const V* __restrict__ vol = volp + bt.voff;
+    const uint8_t* __restrict__ lab = labp + bt.voff;
+    T alp[R];
+    const T* pr[R];
+    T* xr[R];
+    T* zr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        alp[r] = (T)st[bt.sidx * R + r].alpha;
+        const int64_t vb = bt.vbase + src[r] * bt.vstride;
+        pr[r] = (st[bt.sidx * R + src[r]].pcur ? pb1 : pb0) + vb;
+        xr[r] = xv + vb;
+        zr[r] = zv + vb;
+    }
+    Lanes L;
+    L.init(G, bt);
+
+    T Gv[U + 2][VX], Pv[U + 2][R][VX];
+    {
+        const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
+            Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T a = ldu(pr[r] + om.b, L.colb[v]);
+                Pv[0][r][v] = om.inb ? a : T(0);
+                Pv[1][r][v] = ldu(pr[r] + oc.b, L.colb[v]);
+            }
+        }
+    }
+    T wzm[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v)
+        wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
+                     ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
+                     : T(0);
+
+    for (int zb = bt.z0; zb < bt.z1; zb += U) {
+        T Xv[U][R][VX], Zv[U][R][VX];
+        uint8_t Lv[U][VX];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const PlaneOff o = plane_off(G, bt, zb + 1 + k);
+            const PlaneOff oc = plane_off(G, bt, zb + k);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T a = ldu(pr[r] + o.b, L.colb[v]);
+                    Pv[k + 2][r][v] = o.inb ? a : T(0);
+                }
+                Lv[k][v] = ldu(lab + oc.v, L.colv[v]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    Xv[k][r][v] = ldu(xr[r] + oc.b, L.colb[v]);
+                    Zv[k][r][v] = ldu(zr[r] + oc.b, L.colb[v]);
+                }
+            }
+        }
+        T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
+            Ptp[T4 ? U : 1][R][VX];
+        if constexpr (T4) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int lz = zb + k;
+                const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
+                const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
+                    Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T am = ldu(pr[r] + om.b, L.colb[v]);
+                        const T ap = ldu(pr[r] + op.b, L.colb[v]);
+                        Ptm[k][r][v] = im ? am : T(0);
+                        Ptp[k][r][v] = ip ? ap : T(0);
+                    }
+                }
+            }
+        }
+        T hxg, hxp[R];
+        {
+            const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
+            hxg = (T)ldu(vol + o.v, L.hx_colv);
+#pragma unroll
+            for (int r = 0; r < R; ++r) hxp[r] = ldu(pr[r] + o.b, L.hx_colb);
+        }
+        T hyg[NYH][HV], hyp[NYH][R][HV];
+#pragma unroll
+        for (int j = 0; j < NYH; ++j) {
+            const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
+#pragma unroll
+            for (int h = 0; h < HV; ++h) {
+                hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) hyp[j][r][h] = ldu(pr[r] + o.b, L.hy_colb[j][h]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
+            }
+        if (L.hx_use) {
+            sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_box ? hxp[r] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NYH; ++j) {
+            if (L.hy_use[j]) {
+#pragma unroll
+                for (int h = 0; h < HV; ++h) {
+                    const int c = 64 * h + L.lx + 1;
+                    sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
+                            L.hy_box[j][h] ? hyp[j][r][h] : T(0);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int lz = zb + k;
+            const int gz = bt.oz + lz;
+            const bool zin = lz < bt.z1;
+            const int64_t ob = (int64_t)lz * bt.sx * bt.sy;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Stencil<T, Lanes, U, T4> S;
+                S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
+                const T dinv = T(1) / S.d;
+                const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T pc = Pv[k + 1][r][v];
+                    T q;
+                    if constexpr (T4)
+                        q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
+                                      Ptm[k][r][v], Ptp[k][r][v]);
+                    else
+                        q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
+                    const T xn = Xv[k][r][v] + alp[r] * pc;
+                    const T rres = S.d * Zv[k][r][v] - alp[r] * q;
+                    const T zn = dinv * rres;
+                    if (valid && act[r]) {
+                        T* __restrict__ xo = xv + bt.vbase + r * bt.vstride + ob;
+                        T* __restrict__ zo = zv + bt.vbase + r * bt.vstride + ob;
+                        stu(xo, L.colb[v], xn);
+                        stu(zo, L.colb[v], zn);
+                        acc[2 * r] += (double)rres * (double)zn;
+                        acc[2 * r + 1] += (double)rres * (double)rres;
+                    }
+                }
+                wzm[v] = S.wzp;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            Gv[0][v] = Gv[U][v];
+            Gv[1][v] = Gv[U + 1][v];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Pv[0][r][v] = Pv[U][r][v];
+                Pv[1][r][v] = Pv[U + 1][r][v];
+            }
+        }
+    }
+    return true;
+}
+
 template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
           bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
     const T* __restrict__ pb1, const RhsState* __restrict__ st, double* __restrict__ part) {
-    using Lanes = TileLanes<BY, U, VX, YM>;
-    constexpr int NYH = Lanes::NYH;
-    constexpr int HV = Lanes::HV;
-    __shared__ T sg[U][Lanes::TR + 2][Lanes::TC + 2];
-    __shared__ T sp[R][U][Lanes::TR + 2][Lanes::TC + 2];
+    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
         if (!ts.get(it, bt)) continue;
-        bool act[R];
-        int src[R];
-        if (box_labels<R>(st, bt.sidx, act, src) < 0) continue;
-        const Geom& G = bt.G;
-        const V* __restrict__ vol = volp + bt.voff;
-        const uint8_t* __restrict__ lab = labp + bt.voff;
-        T alp[R];
-        const T* pr[R];
-        T* xr[R];
-        T* zr[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            alp[r] = (T)st[bt.sidx * R + r].alpha;
-            const int64_t vb = bt.vbase + src[r] * bt.vstride;
-            pr[r] = (st[bt.sidx * R + src[r]].pcur ? pb1 : pb0) + vb;
-            xr[r] = xv + vb;
-            zr[r] = zv + vb;
-        }
-        Lanes L;
-        L.init(G, bt);
-
-        T Gv[U + 2][VX], Pv[U + 2][R][VX];
-        {
-            const PlaneOff om = plane_off(G, bt, bt.z0 - 1), oc = plane_off(G, bt, bt.z0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = (T)ldu(vol + om.v, L.colv[v]);
-                Gv[1][v] = (T)ldu(vol + oc.v, L.colv[v]);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T a = ldu(pr[r] + om.b, L.colb[v]);
-                    Pv[0][r][v] = om.inb ? a : T(0);
-                    Pv[1][r][v] = ldu(pr[r] + oc.b, L.colb[v]);
-                }
-            }
-        }
-        T wzm[VX];
-#pragma unroll
-        for (int v = 0; v < VX; ++v)
-            wzm[v] = (L.in_box[v] && bt.oz + bt.z0 > 0 && has_zp<T4>(G, bt.oz + bt.z0 - 1))
-                         ? Weight<T>::of(Gv[1][v] - Gv[0][v], wc)
-                         : T(0);
         double acc[2 * R];
 #pragma unroll
         for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
-
-        for (int zb = bt.z0; zb < bt.z1; zb += U) {
-            T Xv[U][R][VX], Zv[U][R][VX];
-            uint8_t Lv[U][VX];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const PlaneOff o = plane_off(G, bt, zb + 1 + k);
-                const PlaneOff oc = plane_off(G, bt, zb + k);
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    Gv[k + 2][v] = (T)ldu(vol + o.v, L.colv[v]);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const T a = ldu(pr[r] + o.b, L.colb[v]);
-                        Pv[k + 2][r][v] = o.inb ? a : T(0);
-                    }
-                    Lv[k][v] = ldu(lab + oc.v, L.colv[v]);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        Xv[k][r][v] = ldu(xr[r] + oc.b, L.colb[v]);
-                        Zv[k][r][v] = ldu(zr[r] + oc.b, L.colb[v]);
-                    }
-                }
-            }
-            T Gtm[T4 ? U : 1][VX], Gtp[T4 ? U : 1][VX], Ptm[T4 ? U : 1][R][VX],
-                Ptp[T4 ? U : 1][R][VX];
-            if constexpr (T4) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int lz = zb + k;
-                    const PlaneOff om = plane_off(G, bt, lz - G.tz), op = plane_off(G, bt, lz + G.tz);
-                    const bool im = lz - G.tz >= 0, ip = lz + G.tz < bt.sz;
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        Gtm[k][v] = (T)ldu(vol + om.v, L.colv[v]);
-                        Gtp[k][v] = (T)ldu(vol + op.v, L.colv[v]);
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const T am = ldu(pr[r] + om.b, L.colb[v]);
-                            const T ap = ldu(pr[r] + op.b, L.colb[v]);
-                            Ptm[k][r][v] = im ? am : T(0);
-                            Ptp[k][r][v] = ip ? ap : T(0);
-                        }
-                    }
-                }
-            }
-            T hxg, hxp[R];
-            {
-                const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
-                hxg = (T)ldu(vol + o.v, L.hx_colv);
-#pragma unroll
-                for (int r = 0; r < R; ++r) hxp[r] = ldu(pr[r] + o.b, L.hx_colb);
-            }
-            T hyg[NYH][HV], hyp[NYH][R][HV];
-#pragma unroll
-            for (int j = 0; j < NYH; ++j) {
-                const PlaneOff o = plane_off(G, bt, zb + L.hy_k[j]);
-#pragma unroll
-                for (int h = 0; h < HV; ++h) {
-                    hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) hyp[j][r][h] = ldu(pr[r] + o.b, L.hy_colb[j][h]);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    sg[k][L.lr[v]][L.lc[v]] = L.in_vol[v] ? Gv[k + 1][v] : T(0);
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        sp[r][k][L.lr[v]][L.lc[v]] = L.in_box[v] ? Pv[k + 1][r][v] : T(0);
-                }
-            if (L.hx_use) {
-                sg[L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_vol ? hxg : T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    sp[r][L.hx_k][L.hx_row_lds][L.hx_col_lds] = L.hx_box ? hxp[r] : T(0);
-            }
-#pragma unroll
-            for (int j = 0; j < NYH; ++j) {
-                if (L.hy_use[j]) {
-#pragma unroll
-                    for (int h = 0; h < HV; ++h) {
-                        const int c = 64 * h + L.lx + 1;
-                        sg[L.hy_k[j]][L.hy_row_lds[j]][c] = L.hy_vol[j][h] ? hyg[j][h] : T(0);
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            sp[r][L.hy_k[j]][L.hy_row_lds[j]][c] =
-                                L.hy_box[j][h] ? hyp[j][r][h] : T(0);
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int lz = zb + k;
-                const int gz = bt.oz + lz;
-                const bool zin = lz < bt.z1;
-                const int64_t ob = (int64_t)lz * bt.sx * bt.sy;
-#pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    Stencil<T, Lanes, U, T4> S;
-                    S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
-                    if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
-                    const T dinv = T(1) / S.d;
-                    const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const T pc = Pv[k + 1][r][v];
-                        T q;
-                        if constexpr (T4)
-                            q = S.apply_t(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v],
-                                          Ptm[k][r][v], Ptp[k][r][v]);
-                        else
-                            q = S.apply(sp[r], k, v, L, wzm[v], pc, Pv[k][r][v], Pv[k + 2][r][v]);
-                        const T xn = Xv[k][r][v] + alp[r] * pc;
-                        const T rres = S.d * Zv[k][r][v] - alp[r] * q;
-                        const T zn = dinv * rres;
-                        if (valid && act[r]) {
-                            T* __restrict__ xo = xv + bt.vbase + r * bt.vstride + ob;
-                            T* __restrict__ zo = zv + bt.vbase + r * bt.vstride + ob;
-                            stu(xo, L.colb[v], xn);
-                            stu(zo, L.colb[v], zn);
-                            acc[2 * r] += (double)rres * (double)zn;
-                            acc[2 * r + 1] += (double)rres * (double)rres;
-                        }
-                    }
-                    wzm[v] = S.wzp;
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                Gv[0][v] = Gv[U][v];
-                Gv[1][v] = Gv[U + 1][v];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    Pv[0][r][v] = Pv[U][r][v];
-                    Pv[1][r][v] = Pv[U + 1][r][v];
-                }
-            }
-        }
+        if (!cg_pass2_tile<V, T, R, BY, U, VX, YM, T4>(smem, bt, volp, labp, wc, xv, zv, pb0, pb1,
+                                                       st, acc))
+            continue;
         block_sum_store<2 * R, BY>(acc, part + bt.pidx, ts.ntiles);
     }
 }
@@ -857,6 +905,295 @@ struct XCell {
 // by the lane that loads it and shared through LDS.  T4 (volume time series,
 // whole volume): the two time neighbours of an own cell, tz planes away, are
 // loaded and formed by its lane.
+template <typename V, int R, int BY, int VX, bool YM>
+struct ResidualSmem {
+    using Lanes = TileLanes<BY, 1, VX, YM>;
+    using GT = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
+    static constexpr size_t cells = size_t(Lanes::TR + 2) * (Lanes::TC + 2);
+    static constexpr size_t bytes = (8 * R + sizeof(GT) + 1) * cells;
+};
+
+// One tile of the float64 residual, accumulated into acc; false if a refresh
+// (mode 2) has no flagged label in the tile's box.  smem: at least
+// ResidualSmem<V, R, BY, VX, YM>::bytes of LDS.
+template <typename V, typename T, int R, int BY, int VX, bool YM = false, bool T4 = false>
+__device__ __forceinline__ bool residual_tile(
+    char* __restrict__ smem, const BoxTile& bt, const V* __restrict__ volp,
+    const uint8_t* __restrict__ labp, WCoef wc, const Shell& sh, int lab0,
+    const double* __restrict__ x64, const double* __restrict__ rhs, T* __restrict__ zv,
+    T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
+    const RhsState* __restrict__ st, double (&acc)[4 * R + 2]) {
+    constexpr int NQ = 4 * R + 2;
+    using Lanes = TileLanes<BY, 1, VX, YM>;
+    constexpr int NYH = Lanes::NYH;
+    constexpr int HV = Lanes::HV;
+    constexpr int LR = Lanes::TR + 2, LC = Lanes::TC + 2;
+    using GT = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
+    using XCells = double[R][LR][LC];
+    using GCells = GT[LR][LC];
+    using DCells = uint8_t[LR][LC];
+    XCells& sx = *reinterpret_cast<XCells*>(smem);
+    GCells& sg = *reinterpret_cast<GCells*>(smem + sizeof(XCells));
+    DCells& sdir = *reinterpret_cast<DCells*>(smem + sizeof(XCells) + sizeof(GCells));
+    (void)NQ;
+    const Geom& G = bt.G;
+    const V* __restrict__ vol = volp + bt.voff;
+    const uint8_t* __restrict__ lab = labp + bt.voff;
+    int wmask = 0;
+    if (mode == 2) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (st[bt.sidx * R + r].outer_active == 2) wmask |= 1 << r;
+        if (!wmask) return false;  // uniform over the block
+    }
+    // labels computed: a refresh (mode 2) needs only the flagged ones,
+    // whose partials alone are read back
+    const int lmask = mode == 2 ? wmask : (1 << R) - 1;
+    Lanes L;
+    L.init(G, bt);
+    const int64_t bplane = (int64_t)bt.sx * bt.sy;
+
+    // Raw values of a cell (intensity, label, float64 iterates); loads
+    // are issued one plane (halo cells) or two planes (own cells) ahead of
+    // the plane being computed, and the cells of the embedding are formed
+    // from them one iteration later, so the loads overlap a plane's work.
+    struct Raw {
+        V g;
+        uint8_t lb;
+        double xb[R];
+    };
+    auto load_raw = [&](int64_t ov, int64_t ob, uint32_t cv, uint32_t cb, Raw& w) {
+        w.g = ldu(vol + ov, cv);
+        w.lb = ldu(lab + ov, cv);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            w.xb[r] = x64 && (lmask & (1 << r)) ? ldu(x64 + bt.vbase + r * bt.vstride + ob, cb)
+                                                : 0.0;
+    };
+    auto load_own = [&](int lz, Raw (&w)[VX]) {
+        const PlaneOff o = plane_off(G, bt, lz);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) load_raw(o.v, o.b, L.colv[v], L.colb[v], w[v]);
+    };
+    auto load_halo = [&](int lz, Raw& wx, Raw (&wy)[NYH][HV]) {
+        const PlaneOff o = plane_off(G, bt, lz);
+        load_raw(o.v, o.b, L.hx_colv, L.hx_colb, wx);
+#pragma unroll
+        for (int j = 0; j < NYH; ++j)
+#pragma unroll
+            for (int h = 0; h < HV; ++h) load_raw(o.v, o.b, L.hy_colv[j][h], L.hy_colb[j][h], wy[j][h]);
+    };
+    auto make_own = [&](int lz, const Raw (&w)[VX], XCell<GT, R> (&c)[VX], uint8_t (&lb)[VX]) {
+        const int gz = bt.oz + lz;
+        const bool zvol = gz >= 0 && gz < G.nz;
+        const bool inb = lz >= 0 && lz < bt.sz;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            lb[v] = w[v].lb;
+            c[v].make((double)w[v].g, w[v].lb, w[v].xb, L.in_vol[v] && zvol, L.in_box[v] && inb,
+                      sh, lab0, bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz, lmask);
+        }
+    };
+
+    XCell<GT, R> cm[VX], cc[VX], cp[VX];
+    uint8_t lbm[VX], lbc[VX], lbp[VX];
+    Raw own1[VX], own2[VX], hx0, hx1, hy0[NYH][HV], hy1[NYH][HV];
+    load_own(bt.z0 - 1, own1);
+    make_own(bt.z0 - 1, own1, cm, lbm);
+    load_own(bt.z0, own1);
+    make_own(bt.z0, own1, cc, lbc);
+    load_own(bt.z0 + 1, own1);
+    load_halo(bt.z0, hx0, hy0);
+    for (int lz = bt.z0; lz < bt.z1; ++lz) {
+        const int gz = bt.oz + lz;
+        const bool zvol = gz >= 0 && gz < G.nz;
+        const bool inb = lz >= 0 && lz < bt.sz;
+        // (A) the next loads: own cells of plane lz+2, halo cells of lz+1
+        load_own(lz + 2, own2);
+        load_halo(lz + 1, hx1, hy1);
+        // (B) cells of plane lz+1 (own) and of plane lz's halo
+        make_own(lz + 1, own1, cp, lbp);
+        XCell<GT, R> hx;
+        hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
+                bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz, lmask);
+        XCell<GT, R> hy[NYH][HV];
+#pragma unroll
+        for (int j = 0; j < NYH; ++j)
+#pragma unroll
+            for (int h = 0; h < HV; ++h)
+                hy[j][h].make((double)hy0[j][h].g, hy0[j][h].lb, hy0[j][h].xb,
+                              L.hy_vol[j][h] && zvol, L.hy_box[j][h] && inb, sh, lab0,
+                              bt.gox + L.gx[0] + 64 * h, bt.goy + L.hy_gy[j], bt.goz + gz,
+                              lmask);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            sg[L.lr[v]][L.lc[v]] = cc[v].g;
+            sdir[L.lr[v]][L.lc[v]] = cc[v].dir;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sx[r][L.lr[v]][L.lc[v]] = cc[v].xt[r];
+        }
+        if (L.hx_use) {
+            sg[L.hx_row_lds][L.hx_col_lds] = hx.g;
+            sdir[L.hx_row_lds][L.hx_col_lds] = hx.dir;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sx[r][L.hx_row_lds][L.hx_col_lds] = hx.xt[r];
+        }
+#pragma unroll
+        for (int j = 0; j < NYH; ++j)
+            if (L.hy_use[j]) {
+#pragma unroll
+                for (int h = 0; h < HV; ++h) {
+                    const int c = 64 * h + L.lx + 1;
+                    sg[L.hy_row_lds[j]][c] = hy[j][h].g;
+                    sdir[L.hy_row_lds[j]][c] = hy[j][h].dir;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) sx[r][L.hy_row_lds[j]][c] = hy[j][h].xt[r];
+                }
+            }
+        __syncthreads();
+        const bool zin = lz < bt.z1;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            if (!(L.in_box[v] && zin)) continue;
+            const uint32_t cb = L.colb[v];
+            const int64_t ob = (int64_t)lz * bplane;
+            if (lbc[v] != 0) {
+                if (mode == 1) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t vb = bt.vbase + r * bt.vstride + ob;
+                        stu(zv + vb, cb, T(0));
+                        stu(p0 + vb, cb, T(0));
+                        stu(p1 + vb, cb, T(0));
+                        if (xi) stu(xi + vb, cb, T(0));
+                    }
+                }
+                continue;
+            }
+            const int c = L.lc[v], rr = L.lr[v];
+            // neighbour order -x, +x, -y, +y, -z, +z (T4: then -t, +t; the
+            // passes sum d in this order)
+            constexpr int NB = T4 ? 8 : 6;
+            XCell<GT, R> ct[2];
+            bool hv[NB];
+            hv[0] = L.gx[v] > 0;
+            hv[1] = L.gx[v] + 1 < G.nx;
+            hv[2] = L.gy[v] > 0;
+            hv[3] = L.gy[v] + 1 < G.ny;
+            hv[4] = gz > 0 && has_zp<T4>(G, gz - 1);
+            hv[5] = has_zp<T4>(G, gz);
+            if constexpr (T4) {
+                hv[6] = gz - G.tz >= 0;
+                hv[7] = gz + G.tz < G.nz;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int lt = h ? lz + G.tz : lz - G.tz;
+                    const PlaneOff ot = plane_off(G, bt, lt);
+                    Raw wt;
+                    load_raw(ot.v, ot.b, L.colv[v], L.colb[v], wt);
+                    ct[h].make((double)wt.g, wt.lb, wt.xb, L.in_vol[v] && hv[6 + h],
+                               L.in_box[v] && ot.inb, sh, lab0, bt.gox + L.gx[v],
+                               bt.goy + L.gy[v], bt.goz + bt.oz + lt, lmask);
+                }
+            }
+            const int ry[6] = {rr, rr, rr - 1, rr + 1, 0, 0};
+            const int rx[6] = {c - 1, c + 1, c, c, 0, 0};
+            double gn[NB];
+            bool dn[NB];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                gn[k] = sg[ry[k]][rx[k]];
+                dn[k] = sdir[ry[k]][rx[k]] != 0;
+            }
+            gn[4] = cm[v].g;
+            dn[4] = cm[v].dir;
+            gn[5] = cp[v].g;
+            dn[5] = cp[v].dir;
+            if constexpr (T4) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    gn[6 + h] = ct[h].g;
+                    dn[6 + h] = ct[h].dir;
+                }
+            }
+            const double gc = cc[v].g;
+            double w[NB];
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                w[k] = hv[k] ? Weight<double>::of(gc - gn[k], wc) : 0.0;
+                d += w[k];
+            }
+            T dT;
+            if constexpr (std::is_same<T, double>::value) {
+                dT = d;
+            } else {
+                T wT[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    wT[k] = hv[k] ? Weight<T>::of((T)gc - (T)gn[k], wc) : T(0);
+                dT = wT[0] + wT[1] + wT[2] + wT[3] + wT[4] + wT[5];
+                if constexpr (T4) dT = dT + wT[6] + wT[7];
+            }
+            if (!(d > 0.0)) acc[4 * R] += 1.0;
+            if (!isfinite(d)) acc[4 * R + 1] += 1.0;
+            const T dinv = T(1) / dT;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!(lmask & (1 << r))) continue;  // uniform over the block
+                const int64_t vb = bt.vbase + r * bt.vstride + ob;
+                double xn[NB];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xn[k] = sx[r][ry[k]][rx[k]];
+                xn[4] = cm[v].xt[r];
+                xn[5] = cp[v].xt[r];
+                if constexpr (T4) {
+                    xn[6] = ct[0].xt[r];
+                    xn[7] = ct[1].xt[r];
+                }
+                const double xc = cc[v].xt[r];
+                double b = rhs ? ldu(rhs + vb, cb) : 0.0;
+                double res = b;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (!hv[k]) continue;
+                    if (dn[k]) b += w[k] * xn[k];
+                    res += w[k] * (xn[k] - xc);
+                }
+                const T rT = (T)res;
+                const T zval = dinv * rT;
+                acc[4 * r + 0] += (double)rT * (double)zval;
+                acc[4 * r + 1] += (double)rT * (double)rT;
+                acc[4 * r + 2] += res * res;
+                acc[4 * r + 3] += b * b;
+                if (mode == 1) {
+                    stu(zv + vb, cb, zval);
+                    stu(p0 + vb, cb, T(0));
+                    stu(p1 + vb, cb, T(0));
+                    if (xi) stu(xi + vb, cb, T(0));
+                } else if (mode == 2 && (wmask & (1 << r))) {
+                    stu(zv + vb, cb, zval);
+                }
+            }
+        }
+        // carry planes lz, lz+1 and the loads in flight
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            cm[v] = cc[v];
+            cc[v] = cp[v];
+            lbc[v] = lbp[v];
+            own1[v] = own2[v];
+        }
+        hx0 = hx1;
+#pragma unroll
+        for (int j = 0; j < NYH; ++j)
+#pragma unroll
+            for (int h = 0; h < HV; ++h) hy0[j][h] = hy1[j][h];
+    }
+    return true;
+}
+
 template <typename V, typename T, int R, int BY, int VX, typename TS, bool YM = false,
           bool T4 = false>
 __global__ __launch_bounds__(64 * BY) void k_residual(
@@ -865,276 +1202,17 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
     T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
     const RhsState* __restrict__ st, double* __restrict__ part) {
     constexpr int NQ = 4 * R + 2;
-    using Lanes = TileLanes<BY, 1, VX, YM>;
-    constexpr int NYH = Lanes::NYH;
-    constexpr int HV = Lanes::HV;
-    constexpr int LR = Lanes::TR + 2, LC = Lanes::TC + 2;
-    using GT = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
-    __shared__ GT sg[LR][LC];
-    __shared__ double sx[R][LR][LC];
-    __shared__ uint8_t sdir[LR][LC];
+    __shared__ __align__(16) char smem[ResidualSmem<V, R, BY, VX, YM>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
         if (!ts.get(it, bt)) continue;
-        const Geom& G = bt.G;
-        const V* __restrict__ vol = volp + bt.voff;
-        const uint8_t* __restrict__ lab = labp + bt.voff;
-        int wmask = 0;
-        if (mode == 2) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (st[bt.sidx * R + r].outer_active == 2) wmask |= 1 << r;
-            if (!wmask) continue;  // uniform over the block
-        }
-        // labels computed: a refresh (mode 2) needs only the flagged ones,
-        // whose partials alone are read back
-        const int lmask = mode == 2 ? wmask : (1 << R) - 1;
-        Lanes L;
-        L.init(G, bt);
-        const int64_t bplane = (int64_t)bt.sx * bt.sy;
         double acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-
-        // Raw values of a cell (intensity, label, float64 iterates); loads
-        // are issued one plane (halo cells) or two planes (own cells) ahead of
-        // the plane being computed, and the cells of the embedding are formed
-        // from them one iteration later, so the loads overlap a plane's work.
-        struct Raw {
-            V g;
-            uint8_t lb;
-            double xb[R];
-        };
-        auto load_raw = [&](int64_t ov, int64_t ob, uint32_t cv, uint32_t cb, Raw& w) {
-            w.g = ldu(vol + ov, cv);
-            w.lb = ldu(lab + ov, cv);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                w.xb[r] = x64 && (lmask & (1 << r)) ? ldu(x64 + bt.vbase + r * bt.vstride + ob, cb)
-                                                    : 0.0;
-        };
-        auto load_own = [&](int lz, Raw (&w)[VX]) {
-            const PlaneOff o = plane_off(G, bt, lz);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) load_raw(o.v, o.b, L.colv[v], L.colb[v], w[v]);
-        };
-        auto load_halo = [&](int lz, Raw& wx, Raw (&wy)[NYH][HV]) {
-            const PlaneOff o = plane_off(G, bt, lz);
-            load_raw(o.v, o.b, L.hx_colv, L.hx_colb, wx);
-#pragma unroll
-            for (int j = 0; j < NYH; ++j)
-#pragma unroll
-                for (int h = 0; h < HV; ++h) load_raw(o.v, o.b, L.hy_colv[j][h], L.hy_colb[j][h], wy[j][h]);
-        };
-        auto make_own = [&](int lz, const Raw (&w)[VX], XCell<GT, R> (&c)[VX], uint8_t (&lb)[VX]) {
-            const int gz = bt.oz + lz;
-            const bool zvol = gz >= 0 && gz < G.nz;
-            const bool inb = lz >= 0 && lz < bt.sz;
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                lb[v] = w[v].lb;
-                c[v].make((double)w[v].g, w[v].lb, w[v].xb, L.in_vol[v] && zvol, L.in_box[v] && inb,
-                          sh, lab0, bt.gox + L.gx[v], bt.goy + L.gy[v], bt.goz + gz, lmask);
-            }
-        };
-
-        XCell<GT, R> cm[VX], cc[VX], cp[VX];
-        uint8_t lbm[VX], lbc[VX], lbp[VX];
-        Raw own1[VX], own2[VX], hx0, hx1, hy0[NYH][HV], hy1[NYH][HV];
-        load_own(bt.z0 - 1, own1);
-        make_own(bt.z0 - 1, own1, cm, lbm);
-        load_own(bt.z0, own1);
-        make_own(bt.z0, own1, cc, lbc);
-        load_own(bt.z0 + 1, own1);
-        load_halo(bt.z0, hx0, hy0);
-        for (int lz = bt.z0; lz < bt.z1; ++lz) {
-            const int gz = bt.oz + lz;
-            const bool zvol = gz >= 0 && gz < G.nz;
-            const bool inb = lz >= 0 && lz < bt.sz;
-            // (A) the next loads: own cells of plane lz+2, halo cells of lz+1
-            load_own(lz + 2, own2);
-            load_halo(lz + 1, hx1, hy1);
-            // (B) cells of plane lz+1 (own) and of plane lz's halo
-            make_own(lz + 1, own1, cp, lbp);
-            XCell<GT, R> hx;
-            hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
-                    bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz, lmask);
-            XCell<GT, R> hy[NYH][HV];
-#pragma unroll
-            for (int j = 0; j < NYH; ++j)
-#pragma unroll
-                for (int h = 0; h < HV; ++h)
-                    hy[j][h].make((double)hy0[j][h].g, hy0[j][h].lb, hy0[j][h].xb,
-                                  L.hy_vol[j][h] && zvol, L.hy_box[j][h] && inb, sh, lab0,
-                                  bt.gox + L.gx[0] + 64 * h, bt.goy + L.hy_gy[j], bt.goz + gz,
-                                  lmask);
-            __syncthreads();
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                sg[L.lr[v]][L.lc[v]] = cc[v].g;
-                sdir[L.lr[v]][L.lc[v]] = cc[v].dir;
-#pragma unroll
-                for (int r = 0; r < R; ++r) sx[r][L.lr[v]][L.lc[v]] = cc[v].xt[r];
-            }
-            if (L.hx_use) {
-                sg[L.hx_row_lds][L.hx_col_lds] = hx.g;
-                sdir[L.hx_row_lds][L.hx_col_lds] = hx.dir;
-#pragma unroll
-                for (int r = 0; r < R; ++r) sx[r][L.hx_row_lds][L.hx_col_lds] = hx.xt[r];
-            }
-#pragma unroll
-            for (int j = 0; j < NYH; ++j)
-                if (L.hy_use[j]) {
-#pragma unroll
-                    for (int h = 0; h < HV; ++h) {
-                        const int c = 64 * h + L.lx + 1;
-                        sg[L.hy_row_lds[j]][c] = hy[j][h].g;
-                        sdir[L.hy_row_lds[j]][c] = hy[j][h].dir;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) sx[r][L.hy_row_lds[j]][c] = hy[j][h].xt[r];
-                    }
-                }
-            __syncthreads();
-            const bool zin = lz < bt.z1;
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                if (!(L.in_box[v] && zin)) continue;
-                const uint32_t cb = L.colb[v];
-                const int64_t ob = (int64_t)lz * bplane;
-                if (lbc[v] != 0) {
-                    if (mode == 1) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const int64_t vb = bt.vbase + r * bt.vstride + ob;
-                            stu(zv + vb, cb, T(0));
-                            stu(p0 + vb, cb, T(0));
-                            stu(p1 + vb, cb, T(0));
-                            if (xi) stu(xi + vb, cb, T(0));
-                        }
-                    }
-                    continue;
-                }
-                const int c = L.lc[v], rr = L.lr[v];
-                // neighbour order -x, +x, -y, +y, -z, +z (T4: then -t, +t; the
-                // passes sum d in this order)
-                constexpr int NB = T4 ? 8 : 6;
-                XCell<GT, R> ct[2];
-                bool hv[NB];
-                hv[0] = L.gx[v] > 0;
-                hv[1] = L.gx[v] + 1 < G.nx;
-                hv[2] = L.gy[v] > 0;
-                hv[3] = L.gy[v] + 1 < G.ny;
-                hv[4] = gz > 0 && has_zp<T4>(G, gz - 1);
-                hv[5] = has_zp<T4>(G, gz);
-                if constexpr (T4) {
-                    hv[6] = gz - G.tz >= 0;
-                    hv[7] = gz + G.tz < G.nz;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int lt = h ? lz + G.tz : lz - G.tz;
-                        const PlaneOff ot = plane_off(G, bt, lt);
-                        Raw wt;
-                        load_raw(ot.v, ot.b, L.colv[v], L.colb[v], wt);
-                        ct[h].make((double)wt.g, wt.lb, wt.xb, L.in_vol[v] && hv[6 + h],
-                                   L.in_box[v] && ot.inb, sh, lab0, bt.gox + L.gx[v],
-                                   bt.goy + L.gy[v], bt.goz + bt.oz + lt, lmask);
-                    }
-                }
-                const int ry[6] = {rr, rr, rr - 1, rr + 1, 0, 0};
-                const int rx[6] = {c - 1, c + 1, c, c, 0, 0};
-                double gn[NB];
-                bool dn[NB];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    gn[k] = sg[ry[k]][rx[k]];
-                    dn[k] = sdir[ry[k]][rx[k]] != 0;
-                }
-                gn[4] = cm[v].g;
-                dn[4] = cm[v].dir;
-                gn[5] = cp[v].g;
-                dn[5] = cp[v].dir;
-                if constexpr (T4) {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        gn[6 + h] = ct[h].g;
-                        dn[6 + h] = ct[h].dir;
-                    }
-                }
-                const double gc = cc[v].g;
-                double w[NB];
-                double d = 0.0;
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    w[k] = hv[k] ? Weight<double>::of(gc - gn[k], wc) : 0.0;
-                    d += w[k];
-                }
-                T dT;
-                if constexpr (std::is_same<T, double>::value) {
-                    dT = d;
-                } else {
-                    T wT[NB];
-#pragma unroll
-                    for (int k = 0; k < NB; ++k)
-                        wT[k] = hv[k] ? Weight<T>::of((T)gc - (T)gn[k], wc) : T(0);
-                    dT = wT[0] + wT[1] + wT[2] + wT[3] + wT[4] + wT[5];
-                    if constexpr (T4) dT = dT + wT[6] + wT[7];
-                }
-                if (!(d > 0.0)) acc[4 * R] += 1.0;
-                if (!isfinite(d)) acc[4 * R + 1] += 1.0;
-                const T dinv = T(1) / dT;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (!(lmask & (1 << r))) continue;  // uniform over the block
-                    const int64_t vb = bt.vbase + r * bt.vstride + ob;
-                    double xn[NB];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) xn[k] = sx[r][ry[k]][rx[k]];
-                    xn[4] = cm[v].xt[r];
-                    xn[5] = cp[v].xt[r];
-                    if constexpr (T4) {
-                        xn[6] = ct[0].xt[r];
-                        xn[7] = ct[1].xt[r];
-                    }
-                    const double xc = cc[v].xt[r];
-                    double b = rhs ? ldu(rhs + vb, cb) : 0.0;
-                    double res = b;
-#pragma unroll
-                    for (int k = 0; k < NB; ++k) {
-                        if (!hv[k]) continue;
-                        if (dn[k]) b += w[k] * xn[k];
-                        res += w[k] * (xn[k] - xc);
-                    }
-                    const T rT = (T)res;
-                    const T zval = dinv * rT;
-                    acc[4 * r + 0] += (double)rT * (double)zval;
-                    acc[4 * r + 1] += (double)rT * (double)rT;
-                    acc[4 * r + 2] += res * res;
-                    acc[4 * r + 3] += b * b;
-                    if (mode == 1) {
-                        stu(zv + vb, cb, zval);
-                        stu(p0 + vb, cb, T(0));
-                        stu(p1 + vb, cb, T(0));
-                        if (xi) stu(xi + vb, cb, T(0));
-                    } else if (mode == 2 && (wmask & (1 << r))) {
-                        stu(zv + vb, cb, zval);
-                    }
-                }
-            }
-            // carry planes lz, lz+1 and the loads in flight
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                cm[v] = cc[v];
-                cc[v] = cp[v];
-                lbc[v] = lbp[v];
-                own1[v] = own2[v];
-            }
-            hx0 = hx1;
-#pragma unroll
-            for (int j = 0; j < NYH; ++j)
-#pragma unroll
-                for (int h = 0; h < HV; ++h) hy0[j][h] = hy1[j][h];
-        }
+        if (!residual_tile<V, T, R, BY, VX, YM, T4>(smem, bt, volp, labp, wc, sh, lab0, x64, rhs,
+                                                    zv, p0, p1, xi, mode, st, acc))
+            continue;
         block_sum_store<NQ, BY>(acc, part + bt.pidx, ts.ntiles);
     }
 }

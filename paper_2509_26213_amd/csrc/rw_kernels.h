@@ -35,6 +35,7 @@ rw_status noalloc_register_device(int device);
 struct TileChoice {
     int by, zc, xcd, vx;
     int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist
+    int persist = 0;    // brick solves: one persistent launch (one block per brick)
 };
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
 // Tile shape of batched brick solves: 64 x (by vx) column tiles, vx rows

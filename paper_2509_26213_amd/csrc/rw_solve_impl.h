@@ -22,6 +22,14 @@ rw_status run_group(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                     const rw_options* o, int lab0, const double* x0, const GroupBuffers& B,
                     void* prob_out, rw_stats* stats, int r_base, int* worst, int tz) {
     const TileChoice tc = choose_tiles(make_geom(vol->dims), o->precision, R);
+    if constexpr (T4) {
+        // time series: two columns per lane, 4 or 8 waves
+        if (tc.by == 8)
+            return run_group_vx<V, T, R, 2, 8, true>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out,
+                                                     stats, r_base, worst, tz);
+        return run_group_vx<V, T, R, 2, 4, true>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out, stats,
+                                                 r_base, worst, tz);
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (tc.vx == 4)
             return run_group_vx<V, T, R, 4, 4, T4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out,
@@ -50,27 +58,42 @@ rw_status dispatch_r(int R, rw_context* ctx, const rw_volume* vol, const uint8_t
     return invalid("bad group size");
 }
 
+// One instantiation per (grid kind, volume type, precision):
+// rw_whole<3|4>_<volume>_<precision>.hip (separate translation units, so
+// they compile in parallel).
+#define RW_WHOLE_DECL(NAME)                                                                  \
+    rw_status NAME(int R, rw_context* ctx, const rw_volume* vol, const uint8_t* lab,         \
+                   const rw_options* o, int lab0, const double* x0, const GroupBuffers& B,   \
+                   void* prob, rw_stats* st, int rb, int* worst, int tz);
+RW_WHOLE_DECL(whole3_u16_f32)
+RW_WHOLE_DECL(whole3_u16_f64)
+RW_WHOLE_DECL(whole3_f32_f32)
+RW_WHOLE_DECL(whole3_f32_f64)
+RW_WHOLE_DECL(whole3_f64_f32)
+RW_WHOLE_DECL(whole3_f64_f64)
+RW_WHOLE_DECL(whole4_u16_f32)
+RW_WHOLE_DECL(whole4_u16_f64)
+RW_WHOLE_DECL(whole4_f32_f32)
+RW_WHOLE_DECL(whole4_f32_f64)
+RW_WHOLE_DECL(whole4_f64_f32)
+RW_WHOLE_DECL(whole4_f64_f64)
+#undef RW_WHOLE_DECL
+
 template <bool T4>
 rw_status dispatch_group(int R, rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                          const rw_options* o, int lab0, const double* x0, const GroupBuffers& B,
                          void* prob, rw_stats* st, int rb, int* worst, int tz) {
-    const bool mixed = o->precision == RW_PREC_MIXED;
+    const bool m = o->precision == RW_PREC_MIXED;
     switch (vol->dtype) {
         case RW_DT_U16:
-            return mixed ? dispatch_r<uint16_t, float, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                           st, rb, worst, tz)
-                         : dispatch_r<uint16_t, double, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                            st, rb, worst, tz);
+            return (T4 ? (m ? whole4_u16_f32 : whole4_u16_f64) : (m ? whole3_u16_f32 : whole3_u16_f64))(
+                R, ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst, tz);
         case RW_DT_F32:
-            return mixed ? dispatch_r<float, float, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob, st,
-                                                        rb, worst, tz)
-                         : dispatch_r<float, double, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                         st, rb, worst, tz);
+            return (T4 ? (m ? whole4_f32_f32 : whole4_f32_f64) : (m ? whole3_f32_f32 : whole3_f32_f64))(
+                R, ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst, tz);
         default:
-            return mixed ? dispatch_r<double, float, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                         st, rb, worst, tz)
-                         : dispatch_r<double, double, T4>(R, ctx, vol, lab, o, lab0, x0, B, prob,
-                                                          st, rb, worst, tz);
+            return (T4 ? (m ? whole4_f64_f32 : whole4_f64_f64) : (m ? whole3_f64_f32 : whole3_f64_f64))(
+                R, ctx, vol, lab, o, lab0, x0, B, prob, st, rb, worst, tz);
     }
 }
 

@@ -92,6 +92,7 @@ TileChoice brick_tiles(int precision, int R, int64_t max_brick_vox) {
     c.vx = env_int("RW_BRICK_VX", c.vx) == 2 ? 2 : 1;  // rows per lane
     c.zc = env_int("RW_BRICK_ZC", c.zc);
     c.brick_xcd = env_int("RW_BRICK_XCD", 0) ? 1 : 0;
+    c.persist = env_int("RW_BRICK_PERSIST", c.persist) ? 1 : 0;
     if (c.by != 4 && c.by != 8 && c.by != 16) c.by = 8;
     if (c.vx == 2 && c.by == 16) c.by = 8;
     if (c.zc < 4) c.zc = 4;

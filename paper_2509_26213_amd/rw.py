@@ -83,7 +83,7 @@ class Stats(ctypes.Structure):
                 ("rhs_iterations", ctypes.c_int64), ("box_voxel_iterations", ctypes.c_int64),
                 ("rhs_voxel_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
                 ("unknowns", ctypes.c_int64), ("tile_vx", ctypes.c_int32),
-                ("tile_xcd", ctypes.c_int32)]
+                ("tile_xcd", ctypes.c_int32), ("brick_blocks", ctypes.c_int32)]
 
     def to_dict(self):
         R = self.num_solved
@@ -97,7 +97,8 @@ class Stats(ctypes.Structure):
                     pass_launches=list(self.pass_launches), rhs_iterations=self.rhs_iterations,
                     box_voxel_iterations=self.box_voxel_iterations,
                     rhs_voxel_iterations=self.rhs_voxel_iterations,
-                    active_bricks=self.active_bricks, unknowns=self.unknowns)
+                    active_bricks=self.active_bricks, unknowns=self.unknowns,
+                    brick_blocks=self.brick_blocks)
 
 
 class SubVolume(ctypes.Structure):

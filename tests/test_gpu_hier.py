@@ -361,3 +361,41 @@ def test_seed_edit_resolve_matches_full_solve(rw, case):
     seeded = new > 0
     for s_ in (1, 2, 3):
         assert np.all(P[s_ - 1][seeded] == (new[seeded] == s_))
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_persistent_brick_kernel_matches_oracle(rw, case, coarse_ref, monkeypatch, K):
+    """The persistent form of the batched brick solve (one launch: each
+    block claims bricks from an atomic queue and runs a brick's whole CG in
+    block-local state), on the default tiles of two and three solved labels:
+    ragged 16^3 and 32^3 bricks against the oracle's brick solves."""
+    monkeypatch.setenv("RW_BRICK_PERSIST", "1")
+    if K == 3:
+        c, g, coarse = case, coarse_ref[0], coarse_ref[3]
+    else:
+        c = blob_case(shape=(45, 70, 90), n_blobs=8, K=4, seeds_per_label=40, sigma=0.06, rmin=5,
+                      rmax=14, seed=53, dtype="u16")
+        g = O.case_g(c)
+        g2, l2 = O.downsample_mean(O.downsample_mean(g)), O.coarse_seeds(O.coarse_seeds(c.labels))
+        coarse = O.random_walker(g2, l2, 4, c.beta, method="pcg", tol=1e-10)
+    for size in ((16, 16, 16), (32, 32, 32)):
+        cands, active = rw.classify_bricks(dev(coarse), dev(c.labels), 4, size, (5, 3, 7))
+        act = [b for b, a in zip(cands, active) if a][:24]
+        prob, iters, st = rw.solve_bricks(dev(c.vol), dev(c.labels), K, c.beta, dev(coarse), 4,
+                                          act, tol=1e-6, precision="mixed", return_stats=True)
+        assert st["status"] == 0 and st["brick_blocks"] > 0, st
+        P = host(prob)
+        for (o, s), it in zip(act, iters):
+            o, s = tuple(o), tuple(s)
+            Pf = np.stack([O.upsample_trilinear(coarse[k], c.shape, 4,
+                                                (tuple(np.array(o) - 1), tuple(np.array(s) + 2)))
+                           for k in range(K)])
+
+            def shell_value(lab_, zz, yy, xx, Pf=Pf, o=o):
+                return Pf[lab_ - 1][zz - o[0] + 1, yy - o[1] + 1, xx - o[2] + 1]
+
+            xb, _ = O.solve_brick(g, c.labels, o, s, shell_value, Pf[1:, 1:-1, 1:-1, 1:-1], c.beta,
+                                  tol=1e-6, solve_labels=list(range(2, K + 1)))
+            sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+            err = np.max(np.abs(P[1:, sl[0], sl[1], sl[2]] - xb))
+            assert err <= 1e-5, (o, s, err, it)
