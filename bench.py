@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="hier1024: run the library's tile autotuners (level-2 whole solve, "
                          "bricks) before timing")
+    ap.add_argument("--tune", action="store_true",
+                    help="only run the library's tile autotuners on the blob512 and hier1024 "
+                         "workloads (their table goes to librw.tune, or RW_TUNE_FILE)")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling runs only: cap CG iterations (the JSON line is then not a "
                          "whole solve)")
@@ -246,6 +249,8 @@ def main():
     from paper_2509_26213_amd import rw
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.tune:
+        return tune_tables(args)
     if args.workload == "hier1024":
         return bench_hier(args)
     if args.workload == "stream2048":
@@ -357,6 +362,7 @@ def main():
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS,
                   "avg_launch_us": ms1 * 1e3 / max(launches1, 1)},
         "tile": tile_key(s["tile"]),
+        "tile_from_autotuner": s["tile_tuned"],
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((ms1 + ms2) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "iters": s["iters"],
         "refinements": s["refinements"],
@@ -382,6 +388,27 @@ def main():
         except Exception as e:  # the sub-object never hides the headline
             result["hier1024"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)
+
+
+def tune_tables(args):
+    """Run the library's autotuners on the benchmark workloads: the whole-
+    volume tiles of blob512 (mixed), and on hier1024 the level-2 whole-volume
+    tiles and the brick tiles.  The library records every winner in its
+    table file (librw.tune beside librw.so, or RW_TUNE_FILE)."""
+    import torch
+    from paper_2509_26213_amd import rw
+    dev = torch.device("cuda:0")
+    case = make_workload("blob512")
+    vol = torch.from_numpy(case.vol).to(dev)
+    lab = torch.from_numpy(case.labels).to(dev)
+    lo, hi = rw.minmax(vol)
+    best = rw.autotune(vol, lab, case.K, case.beta, precision="mixed", lo=lo, hi=hi)
+    print(json.dumps({"tuned": "blob512 whole (vx, zc, xcd, by)", "best": list(best)}), flush=True)
+    del vol, lab
+    torch.cuda.empty_cache()
+    args.autotune = True
+    out = run_hier(args, 1, 0)
+    print(json.dumps({"tuned": "hier1024", "best": out["autotuned"]}), flush=True)
 
 
 def cpu_model():
@@ -556,6 +583,7 @@ def run_hier(args, steps, warmup):
                       "bytes_per_launch": bytes2 / max(b["pass_launches"][1], 1)}),
         "pass1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS},
         "tile": tile_key(b["tile"]) + (" persistent" if persistent else ""),
+        "tile_from_autotuner": b["tile_tuned"],
         "autotuned": tuned,
         "stencil_cg_loop_frac": (bytes1 + bytes2) / ((b["loop_ms"] if persistent else
                                                       b["pass_ms"][0] + b["pass_ms"][1]) * 1e-3)

@@ -141,6 +141,8 @@ typedef struct {
     int32_t tile_xcd;                    /* 1: XCD-aware tile order */
     int32_t brick_blocks;                /* brick solves: blocks of the one persistent
                                             launch (0: one launch per CG pass) */
+    int32_t tile_tuned;                  /* 1: the tile shape came from the autotuner's
+                                            table (librw.tune), 0: the built-in default */
 } rw_stats;
 
 /* Fine-level brick: origin and size in voxels of the fine grid (or of its

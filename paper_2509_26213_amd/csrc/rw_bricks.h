@@ -993,6 +993,7 @@ rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_seeds* see
         stats->tile_vx = BVX;
         stats->tile_xcd = tc.brick_xcd;
         stats->brick_blocks = S.persist_blocks;
+        stats->tile_tuned = tc.tuned;
     }
     if (worst < 0) set_error(std::string("brick solve failed: ") + rw_status_string((rw_status)worst));
     return (rw_status)worst;

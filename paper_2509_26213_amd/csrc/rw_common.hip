@@ -317,6 +317,7 @@ rw_status rw_context_create(rw_context** out) {
     RW_HIP(hipHostMalloc(&c->host_pinned, c->host_pinned_bytes, hipHostMallocDefault));
     c->dev_small_bytes = 1 << 20;
     RW_HIP(hipMalloc(&c->dev_small, c->dev_small_bytes));
+    load_tuning();
     rw_status e = noalloc_register_device(c->device);
     if (e) {
         rw_context_destroy(c);

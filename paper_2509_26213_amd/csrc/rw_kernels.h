@@ -36,7 +36,10 @@ struct TileChoice {
     int by, zc, xcd, vx;
     int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist
     int persist = 0;    // brick solves: one persistent launch (one block per brick)
+    int tuned = 0;      // 1: from the autotuner's table
 };
+// Reads the autotuner's table file once per process (rw_context_create).
+void load_tuning();
 TileChoice tuned_tiles(const Geom& G, int precision, int R);
 // Tile shape of batched brick solves: 64 x (by vx) column tiles, vx rows
 // per lane (1 or 2), by in {4, 8, 16}.

@@ -1,10 +1,15 @@
 // Tile shapes of the stencil kernels: the measured default, the table filled
-// by the autotuner, and overrides.
+// by the autotuner (kept in a text file next to librw.so, so later processes
+// use it), and overrides.
+#include <dlfcn.h>
+
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -29,40 +34,144 @@ int size_class(const Geom& G) {
     return G.n > 0 ? int(std::floor(std::log2(double(G.n)))) : 0;
 }
 
+std::map<std::tuple<int, int, int>, TileChoice> g_brick_tuned;  // (precision, R, size class)
+bool g_table_loaded = false;
+
+// The tuning table file: RW_TUNE_FILE if set (empty: none), else librw.tune
+// beside the loaded librw.so.
+std::string tune_path() {
+    const char* env = std::getenv("RW_TUNE_FILE");
+    if (env) return std::string(env);
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&tune_path), &info) && info.dli_fname) {
+        const std::string p = info.dli_fname;
+        const size_t slash = p.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) +
+               "/librw.tune";
+    }
+    return std::string();
+}
+
+bool valid_whole(const TileChoice& c) {
+    return (c.vx == 1 || c.vx == 2 || c.vx == 4) && (c.by == 4 || (c.by == 8 && c.vx == 2)) &&
+           c.zc >= 4 && c.zc <= 1024 && (c.xcd == 0 || c.xcd == 1);
+}
+
+bool valid_brick(const TileChoice& c) {
+    return (c.vx == 1 || c.vx == 2) && (c.by == 4 || c.by == 8 || (c.by == 16 && c.vx == 1)) &&
+           c.zc >= 4 && c.zc <= 1024 && (c.brick_xcd == 0 || c.brick_xcd == 1) &&
+           (c.persist == 0 || (c.persist == 1 && c.vx == 2 && c.by != 16));
+}
+
+// Lines "whole|brick precision R class by zc xcd vx brick_xcd persist";
+// '#' starts a comment; malformed or invalid lines are skipped.  Called with
+// g_tune_mu held; reads the file once per process.
+void load_table_locked() {
+    if (g_table_loaded) return;
+    g_table_loaded = true;
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#') continue;
+        char kind[16];
+        int prec, R, cls;
+        TileChoice c{4, 32, 0, 1};
+        if (std::sscanf(line, "%15s %d %d %d %d %d %d %d %d %d", kind, &prec, &R, &cls, &c.by,
+                        &c.zc, &c.xcd, &c.vx, &c.brick_xcd, &c.persist) != 10)
+            continue;
+        if ((prec != RW_PREC_FP64 && prec != RW_PREC_MIXED) || R < 1 || R > 4 || cls < 0 ||
+            cls > 62)
+            continue;
+        c.tuned = 1;
+        const auto key = std::make_tuple(prec, R, cls);
+        if (!std::strcmp(kind, "whole") && valid_whole(c)) g_tuned[key] = c;
+        if (!std::strcmp(kind, "brick") && valid_brick(c)) g_brick_tuned[key] = c;
+    }
+    std::fclose(f);
+}
+
+// Rewrite the file with the whole table (called with g_tune_mu held after a
+// tuner run); failures to write leave the in-process table in place.
+void save_table_locked() {
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "# librw tile table, written by rw_autotune / rw_autotune_bricks\n");
+    std::fprintf(f, "# kind precision(0 fp64, 1 mixed) solved_labels size_class(floor log2 "
+                    "voxels) by zc xcd vx brick_xcd persist\n");
+    for (const auto& kv : g_tuned)
+        std::fprintf(f, "whole %d %d %d %d %d %d %d %d %d\n", std::get<0>(kv.first),
+                     std::get<1>(kv.first), std::get<2>(kv.first), kv.second.by, kv.second.zc,
+                     kv.second.xcd, kv.second.vx, kv.second.brick_xcd, kv.second.persist);
+    for (const auto& kv : g_brick_tuned)
+        std::fprintf(f, "brick %d %d %d %d %d %d %d %d %d\n", std::get<0>(kv.first),
+                     std::get<1>(kv.first), std::get<2>(kv.first), kv.second.by, kv.second.zc,
+                     kv.second.xcd, kv.second.vx, kv.second.brick_xcd, kv.second.persist);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path.c_str());
+    else std::remove(tmp.c_str());
+}
+
+bool env_set(const char* name) {
+    const char* v = std::getenv(name);
+    return v && *v;
+}
+
 }  // namespace
 
+void load_tuning() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_table_locked();
+}
+
+// Precedence: a shape forced by the autotuner while it times candidates,
+// then RW_TILE_* overrides, then the autotuner's table, then the measured
+// default.
 TileChoice tuned_tiles(const Geom& G, int precision, int R) {
     if (g_forced) return g_force;
+    TileChoice c{4, 32, 0, 2};
+    bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_table_locked();
         auto it = g_tuned.find(std::make_tuple(precision, R, size_class(G)));
-        if (it != g_tuned.end()) return it->second;
+        if (it != g_tuned.end()) {
+            c = it->second;
+            have = true;
+        }
     }
-    // measured on MI355X: two columns per lane (128-wide tiles) beat one and
-    // four in both precisions.  Float32 passes of two labels run fastest on
-    // 128 x 8 x 64 tiles (8 waves; 2 % over 128 x 4 x 32 on 512^3, whose
-    // y-halo rows, half of the tile again, all miss L2) when the volume holds
-    // at least 1024 of them; with three or more labels the passes fit three
-    // or fewer waves per SIMD, so an 8-wave tile leaves a slot idle (three
-    // labels on 512 x 512 x 256: 4 % slower) and 128 x 4 x 32 in XCD-aware
-    // order stays.  Float64 passes: 128 x 4 x 32 in plain order (128 x 8
-    // loses 6-10 %).
-    TileChoice c{4, 32, 0, 2};
-    if (precision == RW_PREC_MIXED) {
+    if (!have && precision == RW_PREC_MIXED) {
+        // measured on MI355X: two columns per lane (128-wide tiles) beat one and
+        // four in both precisions.  Float32 passes of two labels run fastest on
+        // 128 x 8 x 64 tiles (8 waves; 2 % over 128 x 4 x 32 on 512^3, whose
+        // y-halo rows, half of the tile again, all miss L2) when the volume holds
+        // at least 1024 of them; with three or more labels the passes fit three
+        // or fewer waves per SIMD, so an 8-wave tile leaves a slot idle (three
+        // labels on 512 x 512 x 256: 4 % slower) and 128 x 4 x 32 in XCD-aware
+        // order stays.  Float64 passes: 128 x 4 x 32 in plain order (128 x 8
+        // loses 6-10 %).
         const int64_t tall = int64_t((G.nx + 127) / 128) * ((G.ny + 7) / 8) * ((G.nz + 63) / 64);
         c = R == 2 && tall >= 1024 ? TileChoice{8, 64, 0, 2} : TileChoice{4, 32, 1, 2};
     }
-    c.vx = env_int("RW_TILE_VX", c.vx);
-    c.zc = env_int("RW_TILE_ZC", c.zc);
-    c.xcd = env_int("RW_TILE_XCD", c.xcd);
-    c.by = env_int("RW_TILE_BY", c.by);
+    if (env_set("RW_TILE_VX") || env_set("RW_TILE_ZC") || env_set("RW_TILE_XCD") ||
+        env_set("RW_TILE_BY")) {
+        c.vx = env_int("RW_TILE_VX", c.vx);
+        c.zc = env_int("RW_TILE_ZC", c.zc);
+        c.xcd = env_int("RW_TILE_XCD", c.xcd);
+        c.by = env_int("RW_TILE_BY", c.by);
+        c.tuned = 0;
+    }
     if (c.zc < 4) c.zc = 4;
     return c;
 }
 
 namespace {
 
-std::map<std::tuple<int, int, int>, TileChoice> g_brick_tuned;  // (precision, R, size class)
 thread_local bool g_brick_forced = false;
 thread_local TileChoice g_brick_force{8, 64, 0, 2};
 
@@ -72,10 +181,15 @@ int brick_class(int64_t max_vox) {
 
 }  // namespace
 
+// Precedence as for tuned_tiles: a candidate forced by the autotuner, then
+// RW_BRICK_* overrides, then the autotuner's table, then the default.
 TileChoice brick_tiles(int precision, int R, int64_t max_brick_vox) {
     if (g_brick_forced) return g_brick_force;
-    {
+    const bool env = env_set("RW_BRICK_BY") || env_set("RW_BRICK_VX") || env_set("RW_BRICK_ZC") ||
+                     env_set("RW_BRICK_XCD") || env_set("RW_BRICK_PERSIST");
+    if (!env) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_table_locked();
         auto it = g_brick_tuned.find(std::make_tuple(precision, R, brick_class(max_brick_vox)));
         if (it != g_brick_tuned.end()) return it->second;
     }
@@ -167,7 +281,10 @@ rw_status rw_autotune(rw_context* ctx, const rw_volume* vol, const rw_seeds* see
                 }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_table_locked();
+        win.tuned = 1;
         g_tuned[std::make_tuple(opts->precision, R, size_class(G))] = win;
+        save_table_locked();
     }
     if (best) {
         best[0] = win.vx;
@@ -215,7 +332,10 @@ rw_status rw_autotune_bricks(rw_context* ctx, const rw_volume* fine, const rw_se
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_table_locked();
+        win.tuned = 1;
         g_brick_tuned[std::make_tuple(opts->precision, R, brick_class(max_vox))] = win;
+        save_table_locked();
     }
     if (best) {
         best[0] = win.by;

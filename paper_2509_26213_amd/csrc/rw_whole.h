@@ -610,6 +610,7 @@ inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8
         stats->tile_zc = S.tm.zc;
         stats->tile_vx = VX;
         stats->tile_xcd = S.tm.xcd;
+        stats->tile_tuned = tc.tuned;
     }
     if (*worst < 0) return RW_OK;  // caller reports, outputs untouched
     const int64_t n = S.G.n;

@@ -7,6 +7,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# tests neither read nor write the library's tile table file (librw.tune):
+# autotuner tests would otherwise rewrite it, and a table entry would take
+# the place of the built-in tiles the tests expect
+os.environ.setdefault("RW_TUNE_FILE", "")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

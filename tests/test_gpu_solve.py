@@ -1,12 +1,16 @@
 """GPU parity of the whole-volume solve (librw.so through the C ABI) against
 the CPU oracle: weights, the matrix-free operator, FP64 and mixed Jacobi-PCG,
 edge cases and error statuses."""
+import os
+
 import numpy as np
 import pytest
 
 from oracle import rw_oracle as O
 from synth import blob_case, random_case, sphere_case
 from tests._helpers import assert_parity, dev, host
+
+ROOT_DIR = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -310,3 +314,47 @@ def test_autotuner_records_a_tile_and_solves_agree(rw):
     prob, _, st = rw.solve(vol, lab, 3, c.beta, precision="mixed", return_stats=True)
     assert st["tile"]["vx"] == vx and st["tile"]["xcd"] == xcd and st["tile"]["by"] == by
     assert_parity(host(prob), ref, what="after autotune")
+
+
+def test_tile_table_file_is_written_and_read_by_later_processes(tmp_path):
+    """The autotuner's table outlives its process: a child process tunes a
+    volume (RW_TUNE_FILE = a fresh file) and the file then names the shape;
+    a second child process solves the same volume and reports the tuned shape
+    as coming from the table; with RW_TUNE_FILE empty the built-in shape is
+    used."""
+    import json
+    import subprocess
+    import sys
+    import textwrap
+    path = tmp_path / "librw.tune"
+    code = textwrap.dedent("""
+        import json, sys
+        import numpy as np
+        sys.path.insert(0, %r)
+        from synth import blob_case
+        from paper_2509_26213_amd import rw
+        from tests._helpers import dev
+        c = blob_case(shape=(40, 60, 200), n_blobs=6, K=3, seeds_per_label=30, sigma=0.06,
+                      rmin=5, rmax=12, seed=91)
+        vol, lab = dev(c.vol), dev(c.labels)
+        best = rw.autotune(vol, lab, 3, c.beta, precision="mixed") if sys.argv[1] == "tune" else None
+        _, _, st = rw.solve(vol, lab, 3, c.beta, precision="mixed", return_stats=True)
+        print(json.dumps(dict(best=best, tile=st["tile"], tuned=st["tile_tuned"])))
+    """ % ROOT_DIR)
+    env = dict(os.environ, RW_TUNE_FILE=str(path))
+    first = subprocess.run([sys.executable, "-c", code, "tune"], env=env, capture_output=True,
+                           text=True, timeout=600)
+    assert first.returncode == 0, first.stderr[-2000:]
+    r1 = json.loads(first.stdout.strip().splitlines()[-1])
+    assert path.exists() and "whole 1 2 " in path.read_text()
+    second = subprocess.run([sys.executable, "-c", code, "solve"], env=env, capture_output=True,
+                            text=True, timeout=600)
+    assert second.returncode == 0, second.stderr[-2000:]
+    r2 = json.loads(second.stdout.strip().splitlines()[-1])
+    vx, zc, xcd, by = r1["best"]
+    assert r2["tuned"] and r2["tile"] == dict(vx=vx, by=by, zc=r2["tile"]["zc"], xcd=xcd)
+    off = subprocess.run([sys.executable, "-c", code, "solve"],
+                         env=dict(os.environ, RW_TUNE_FILE=""), capture_output=True, text=True,
+                         timeout=600)
+    assert off.returncode == 0, off.stderr[-2000:]
+    assert not json.loads(off.stdout.strip().splitlines()[-1])["tuned"]
