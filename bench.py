@@ -764,8 +764,9 @@ def bench_grad(args):
 
 
 def bench_stream(args):
-    """Out-of-core-shaped workload (2048x2048x1024 uint16, K = 4, 1024 blobs,
-    4000 seeds per label, counter-based noise): the volume is generated in
+    """Out-of-core-shaped workload (2048x2048x1024 uint16, K = 4, 256 blobs
+    (the blob density of the hierarchical workload), 4000 seeds per label,
+    counter-based noise): the volume is generated in
     host memory (threads over z-slabs, not timed), then one streamed
     hierarchical solve: level 1 built brick by brick from pinned
     double-buffered H2D copies, level 2 (512x512x256) solved whole, 128^3
@@ -782,7 +783,7 @@ def bench_stream(args):
     from synth.volumes import brickwise_blob_case
 
     t0 = time.perf_counter()
-    case = brickwise_blob_case(shape=(1024, 2048, 2048), n_blobs=1024, K=4, seeds_per_label=4000,
+    case = brickwise_blob_case(shape=(1024, 2048, 2048), n_blobs=256, K=4, seeds_per_label=4000,
                                sigma=0.08, bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=5)
     shape = case.shape
     vol = np.empty(shape, np.uint16)
@@ -820,7 +821,7 @@ def bench_stream(args):
         "steps": 1, "warmup": 0, "ms_per_step": sec * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64dot", "data": "synthetic",
         "config": {"workload": "stream2048: 2048x2048x1024 uint16 blob volume generated brick-wise "
-                               "(1024 blobs, 4000 seeds per label, K=4, beta 150) in host memory, "
+                               "(256 blobs, 4000 seeds per label, K=4, beta 150) in host memory, "
                                "level-2 512x512x256 solved whole, 128^3 bricks streamed through "
                                f"two device pools of {args.pool}, mixed, tol 1e-6, labels out",
                    "voxels": n_vox, "bricks": info["bricks"],
@@ -832,6 +833,7 @@ def bench_stream(args):
         "coarse_iters": info["coarse_iters"],
         "brick_iters_median": float(np.median(its)), "brick_iters_max": int(its.max()),
         "pcie": {"h2d_bytes": info["h2d_bytes"], "d2h_bytes": info["d2h_bytes"]},
+        "seeds_on_device": info["seeds"],
         "checks": {"seeds_exact": seeds_exact, "labels_in_range": in_range},
     }), flush=True)
 

@@ -280,6 +280,45 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
                              double hi_thr, rw_brick* bricks_out, uint8_t* active_out,
                              int32_t capacity, int32_t* n_candidates, void* stream);
 
+/* rw_classify_bricks with the seed rule taken from a seed list instead of a
+ * dense fine label map (the out-of-core form: the fine labels need not be
+ * on the device).  seed_index: device int64 [n_seeds], flat fine-grid
+ * indices (z * ny + y) * nx + x; seed_label: device uint8 [n_seeds], 1..K.
+ * Entries outside the grid or with label 0 are ignored.  The result equals
+ * rw_classify_bricks on the label map holding exactly these seeds. */
+rw_status rw_classify_bricks_sparse(rw_context* ctx, const void* coarse_prob,
+                                    int32_t coarse_dtype, rw_dims coarse_dims, int32_t num_labels,
+                                    int32_t factor, const int64_t* seed_index,
+                                    const uint8_t* seed_label, int64_t n_seeds, rw_dims fine_dims,
+                                    const int32_t brick_size[3], const int32_t grid_offset[3],
+                                    double lo_thr, double hi_thr, rw_brick* bricks_out,
+                                    uint8_t* active_out, int32_t capacity, int32_t* n_candidates,
+                                    void* stream);
+
+/* What a seed edit reaches, for an incremental re-solve of a hierarchical
+ * solution (the paper's interactive segmentation, Sec. IV-B): on the brick
+ * grid of rw_classify_bricks (same brick_size, grid_offset; candidates in
+ * the same order),
+ *   edited_out[b] = 1 if brick b holds a voxel whose label differs between
+ *     old_labels and new_labels, or one of such a voxel's six face
+ *     neighbours (its face shell holds the voxel), else 0;
+ *   moved_out[b] = the largest |new_coarse - old_coarse| over the K labels
+ *     and over the coarse cells of b's footprint (fine origin / factor to
+ *     ceil(fine end / factor)) and one cell around it.
+ * old_labels, new_labels: device uint8 fine label maps; old_coarse,
+ * new_coarse: device [K][coarse dims] of coarse_dtype (F32 or F64).
+ * edited_out (uint8), moved_out (double): host arrays of capacity >=
+ * candidates; *n_candidates receives the count (a call with capacity 0
+ * only counts, returning RW_ERR_INVALID_ARG). */
+rw_status rw_seed_edit_bricks(rw_context* ctx, const uint8_t* old_labels,
+                              const uint8_t* new_labels, rw_dims fine_dims,
+                              const void* old_coarse, const void* new_coarse,
+                              int32_t coarse_dtype, rw_dims coarse_dims, int32_t num_labels,
+                              int32_t factor, const int32_t brick_size[3],
+                              const int32_t grid_offset[3], uint8_t* edited_out,
+                              double* moved_out, int32_t capacity, int32_t* n_candidates,
+                              void* stream);
+
 /* Batched solve of many bricks of the fine level in one set of launches
  * (each CG pass of every brick in one launch, over a compacted list of the
  * tiles of the bricks still iterating; per-brick, per-label convergence).

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_classify(Shell sh, int K, Geom F,
             }
             if (x < 0 || x >= F.nx || y < 0 || y >= F.ny || z < 0 || z >= F.nz) continue;
         }
-        const uint8_t l = in_brick ? lab[(int64_t)z * F.plane + (int64_t)y * F.nx + x] : 0;
+        const uint8_t l = in_brick && lab ? lab[(int64_t)z * F.plane + (int64_t)y * F.nx + x] : 0;
         double best = -1.0;
         int arg = 1;
         bool unc = false;
@@ -132,6 +132,104 @@ __global__ __launch_bounds__(256) void k_classify(Shell sh, int K, Geom F,
     }
     __syncthreads();
     if (threadIdx.x == 0) flags[blockIdx.x] = found ? 1 : 0;
+}
+
+// Index of the candidate brick holding coordinate p along one axis: cuts at
+// o (if o > 0), then every b voxels.
+__device__ __forceinline__ int cut_index(int p, int b, int o) {
+    return o > 0 ? (p < o ? 0 : 1 + (p - o) / b) : p / b;
+}
+
+// The seed rule of the activity test from a seed list: a brick is active if
+// one of its seeds has a label other than the upsampled argmax (lowest label
+// on ties) at that voxel.  One thread per seed; seeds outside the grid are
+// ignored.
+__global__ __launch_bounds__(256) void k_seed_bricks(Shell sh, int K, Geom F,
+                                                     const int64_t* __restrict__ sidx,
+                                                     const uint8_t* __restrict__ slab, int64_t ns,
+                                                     int bx, int by, int bz, int ox, int oy,
+                                                     int oz, int ncx, int ncy,
+                                                     uint8_t* __restrict__ flags) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < ns; i += 256ll * gridDim.x) {
+        const int64_t g = sidx[i];
+        const uint8_t l = slab[i];
+        if (g < 0 || g >= F.n || l == 0) continue;
+        const int z = int(g / F.plane);
+        const int64_t r = g - (int64_t)z * F.plane;
+        const int y = int(r / F.nx);
+        const int x = int(r - (int64_t)y * F.nx);
+        double best = -1.0;
+        int arg = 1;
+        for (int L = 1; L <= K; ++L) {
+            const double p = upsample(sh, L, x, y, z);
+            if (p > best) {
+                best = p;
+                arg = L;
+            }
+        }
+        if (l != arg) {
+            const int64_t b = ((int64_t)cut_index(z, bz, oz) * ncy + cut_index(y, by, oy)) * ncx +
+                              cut_index(x, bx, ox);
+            flags[b] = 1;
+        }
+    }
+}
+
+// Bricks a seed edit reaches: for every fine voxel whose label changed, the
+// brick holding it and the bricks holding one of its six face neighbours
+// (the bricks whose face shell holds it).  Grid-stride over the voxels.
+__global__ __launch_bounds__(256) void k_edit_bricks(const uint8_t* __restrict__ old_l,
+                                                     const uint8_t* __restrict__ new_l, Geom F,
+                                                     int bx, int by, int bz, int ox, int oy,
+                                                     int oz, int ncx, int ncy,
+                                                     uint8_t* __restrict__ flags) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < F.n; i += 256ll * gridDim.x) {
+        if (old_l[i] == new_l[i]) continue;
+        const int z = int(i / F.plane);
+        const int64_t r = i - (int64_t)z * F.plane;
+        const int y = int(r / F.nx);
+        const int x = int(r - (int64_t)y * F.nx);
+        const int dx[7] = {0, -1, 1, 0, 0, 0, 0}, dy[7] = {0, 0, 0, -1, 1, 0, 0},
+                  dz[7] = {0, 0, 0, 0, 0, -1, 1};
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int px = x + dx[k], py = y + dy[k], pz = z + dz[k];
+            if (px < 0 || px >= F.nx || py < 0 || py >= F.ny || pz < 0 || pz >= F.nz) continue;
+            const int64_t b = ((int64_t)cut_index(pz, bz, oz) * ncy + cut_index(py, by, oy)) * ncx +
+                              cut_index(px, bx, ox);
+            flags[b] = 1;
+        }
+    }
+}
+
+// How far the coarse solution moved under each brick: the largest
+// |new - old| over the labels and over the coarse cells of the brick's
+// footprint and one cell around it.  One block per candidate brick.
+__global__ __launch_bounds__(256) void k_coarse_moved(Shell olds, Shell news, int K,
+                                                      const DevBrick* __restrict__ cand,
+                                                      double* __restrict__ moved) {
+    const DevBrick b = cand[blockIdx.x];
+    const int f = news.factor;
+    const int x0 = max(0, b.ox / f - 1), x1 = min(news.cnx, (b.ox + b.sx + f - 1) / f + 1);
+    const int y0 = max(0, b.oy / f - 1), y1 = min(news.cny, (b.oy + b.sy + f - 1) / f + 1);
+    const int z0 = max(0, b.oz / f - 1), z1 = min(news.cnz, (b.oz + b.sz + f - 1) / f + 1);
+    const int64_t wx = x1 - x0, wy = y1 - y0, cells = wx * wy * (z1 - z0);
+    double m = 0.0;
+    for (int64_t c = threadIdx.x; c < cells * K; c += 256) {
+        const int L = int(c / cells);
+        const int64_t j = c - (int64_t)L * cells;
+        const int z = z0 + int(j / (wx * wy));
+        const int64_t r = j % (wx * wy);
+        const int y = y0 + int(r / wx), x = x0 + int(r % wx);
+        const int64_t idx = (int64_t)L * news.cn + ((int64_t)z * news.cny + y) * news.cnx + x;
+        m = fmax(m, fabs(coarse_at(news, idx) - coarse_at(olds, idx)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    __shared__ double wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) moved[blockIdx.x] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
 }
 
 // Upsampled probabilities (seeds exact) for every voxel of the listed bricks
@@ -229,15 +327,18 @@ rw_status rw_downsample(rw_context* ctx, const rw_volume* fine, const uint8_t* f
     return stream_leave(ctx, stream);
 }
 
-rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
-                             rw_dims coarse_dims, int32_t num_labels, int32_t factor,
-                             const uint8_t* fine_labels, rw_dims fine_dims,
-                             const int32_t brick_size[3], const int32_t grid_offset[3],
-                             double lo_thr, double hi_thr, rw_brick* bricks_out,
-                             uint8_t* active_out, int32_t capacity, int32_t* n_candidates,
-                             void* stream) {
-    if (!ctx || !fine_labels || !brick_size || !grid_offset || !n_candidates)
-        return invalid("NULL argument");
+}  // extern "C"
+
+// Brick activity from the coarse probabilities, with the seed rule taken
+// from a dense fine label map (labels) or from a seed list (sidx, slab).
+static rw_status classify_impl(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
+                               rw_dims coarse_dims, int32_t num_labels, int32_t factor,
+                               const uint8_t* labels, const int64_t* sidx, const uint8_t* slab,
+                               int64_t n_seeds, rw_dims fine_dims, const int32_t brick_size[3],
+                               const int32_t grid_offset[3], double lo_thr, double hi_thr,
+                               rw_brick* bricks_out, uint8_t* active_out, int32_t capacity,
+                               int32_t* n_candidates, void* stream) {
+    if (!ctx || !brick_size || !grid_offset || !n_candidates) return invalid("NULL argument");
     if (num_labels < 1 || num_labels > RW_MAX_LABELS) return invalid("num_labels must be in [1, 16]");
     if (!dims_supported(fine_dims)) return invalid("fine dims must be positive and supported");
     for (int a = 0; a < 3; ++a)
@@ -265,9 +366,15 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
     if ((e = stream_enter(ctx, stream))) return e;
     DevBrick* dc = static_cast<DevBrick*>(ctx->dev_small);
     uint8_t* flags = reinterpret_cast<uint8_t*>(dc + n);
+    const Geom F = make_geom(fine_dims);
     RW_HIP(hipMemcpyAsync(dc, cand.data(), sizeof(DevBrick) * n, hipMemcpyHostToDevice, ctx->s));
-    hipLaunchKernelGGL(k_classify, dim3(unsigned(n)), dim3(256), 0, ctx->s, sh, num_labels,
-                       make_geom(fine_dims), fine_labels, dc, lo_thr, hi_thr, flags);
+    hipLaunchKernelGGL(k_classify, dim3(unsigned(n)), dim3(256), 0, ctx->s, sh, num_labels, F,
+                       labels, dc, lo_thr, hi_thr, flags);
+    if (n_seeds > 0)
+        hipLaunchKernelGGL(k_seed_bricks, dim3(unsigned(std::min<int64_t>((n_seeds + 255) / 256, 4096))),
+                           dim3(256), 0, ctx->s, sh, num_labels, F, sidx, slab, n_seeds,
+                           brick_size[0], brick_size[1], brick_size[2], grid_offset[0],
+                           grid_offset[1], grid_offset[2], int(cx.size()), int(cy.size()), flags);
     RW_HIP(hipGetLastError());
     if ((e = ensure_host_pinned(ctx, size_t(n)))) return e;
     RW_HIP(hipMemcpyAsync(ctx->host_pinned, flags, n, hipMemcpyDeviceToHost, ctx->s));
@@ -276,6 +383,96 @@ rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t c
     for (int64_t i = 0; i < n; ++i)
         bricks_out[i] = rw_brick{cand[i].ox, cand[i].oy, cand[i].oz, cand[i].sx, cand[i].sy, cand[i].sz};
     return stream_leave(ctx, stream);
+}
+
+extern "C" {
+
+rw_status rw_classify_bricks(rw_context* ctx, const void* coarse_prob, int32_t coarse_dtype,
+                             rw_dims coarse_dims, int32_t num_labels, int32_t factor,
+                             const uint8_t* fine_labels, rw_dims fine_dims,
+                             const int32_t brick_size[3], const int32_t grid_offset[3],
+                             double lo_thr, double hi_thr, rw_brick* bricks_out,
+                             uint8_t* active_out, int32_t capacity, int32_t* n_candidates,
+                             void* stream) {
+    if (!fine_labels) return invalid("fine_labels is NULL");
+    return classify_impl(ctx, coarse_prob, coarse_dtype, coarse_dims, num_labels, factor,
+                         fine_labels, nullptr, nullptr, 0, fine_dims, brick_size, grid_offset,
+                         lo_thr, hi_thr, bricks_out, active_out, capacity, n_candidates, stream);
+}
+
+rw_status rw_seed_edit_bricks(rw_context* ctx, const uint8_t* old_labels,
+                              const uint8_t* new_labels, rw_dims fine_dims,
+                              const void* old_coarse, const void* new_coarse,
+                              int32_t coarse_dtype, rw_dims coarse_dims, int32_t num_labels,
+                              int32_t factor, const int32_t brick_size[3],
+                              const int32_t grid_offset[3], uint8_t* edited_out,
+                              double* moved_out, int32_t capacity, int32_t* n_candidates,
+                              void* stream) {
+    if (!ctx || !old_labels || !new_labels || !brick_size || !grid_offset || !n_candidates)
+        return invalid("NULL argument");
+    if (num_labels < 1 || num_labels > RW_MAX_LABELS) return invalid("num_labels must be in [1, 16]");
+    if (!dims_supported(fine_dims)) return invalid("fine dims must be positive and supported");
+    for (int a = 0; a < 3; ++a)
+        if (brick_size[a] < 1 || grid_offset[a] < 0) return invalid("bad brick size or offset");
+    Shell so, sn;
+    rw_status e = make_shell(old_coarse, coarse_dtype, coarse_dims, factor, &so);
+    if (e) return e;
+    if ((e = make_shell(new_coarse, coarse_dtype, coarse_dims, factor, &sn))) return e;
+    const auto cx = cuts(int(fine_dims.nx), brick_size[0], grid_offset[0]);
+    const auto cy = cuts(int(fine_dims.ny), brick_size[1], grid_offset[1]);
+    const auto cz = cuts(int(fine_dims.nz), brick_size[2], grid_offset[2]);
+    const int64_t n = (int64_t)cx.size() * cy.size() * cz.size();
+    *n_candidates = int32_t(n);
+    if (!edited_out || !moved_out || capacity < n) {
+        set_error("capacity must hold " + std::to_string(n) + " candidate bricks");
+        return RW_ERR_INVALID_ARG;
+    }
+    std::vector<DevBrick> cand;
+    cand.reserve(n);
+    for (auto& z : cz)
+        for (auto& y : cy)
+            for (auto& x : cx)
+                cand.push_back(DevBrick{x.first, y.first, z.first, x.second, y.second, z.second,
+                                        int(fine_dims.nx), int(fine_dims.ny), 0, 0, 0, 0});
+    const size_t bytes = sizeof(DevBrick) * n + sizeof(double) * n + n + 256;
+    if ((e = ensure_dev_small(ctx, bytes))) return e;
+    if ((e = ensure_host_pinned(ctx, sizeof(double) * n + n))) return e;
+    if ((e = stream_enter(ctx, stream))) return e;
+    DevBrick* dc = static_cast<DevBrick*>(ctx->dev_small);
+    double* moved = reinterpret_cast<double*>(dc + n);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(moved + n);
+    const Geom F = make_geom(fine_dims);
+    RW_HIP(hipMemcpyAsync(dc, cand.data(), sizeof(DevBrick) * n, hipMemcpyHostToDevice, ctx->s));
+    RW_HIP(hipMemsetAsync(flags, 0, n, ctx->s));
+    hipLaunchKernelGGL(k_edit_bricks, dim3(unsigned(std::min<int64_t>((F.n + 255) / 256, 8192))),
+                       dim3(256), 0, ctx->s, old_labels, new_labels, F, brick_size[0],
+                       brick_size[1], brick_size[2], grid_offset[0], grid_offset[1],
+                       grid_offset[2], int(cx.size()), int(cy.size()), flags);
+    hipLaunchKernelGGL(k_coarse_moved, dim3(unsigned(n)), dim3(256), 0, ctx->s, so, sn,
+                       num_labels, dc, moved);
+    RW_HIP(hipGetLastError());
+    char* hp = static_cast<char*>(ctx->host_pinned);
+    RW_HIP(hipMemcpyAsync(hp, moved, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->s));
+    RW_HIP(hipMemcpyAsync(hp + sizeof(double) * n, flags, n, hipMemcpyDeviceToHost, ctx->s));
+    RW_HIP(hipStreamSynchronize(ctx->s));
+    memcpy(moved_out, hp, sizeof(double) * n);
+    memcpy(edited_out, hp + sizeof(double) * n, n);
+    return stream_leave(ctx, stream);
+}
+
+rw_status rw_classify_bricks_sparse(rw_context* ctx, const void* coarse_prob,
+                                    int32_t coarse_dtype, rw_dims coarse_dims, int32_t num_labels,
+                                    int32_t factor, const int64_t* seed_index,
+                                    const uint8_t* seed_label, int64_t n_seeds, rw_dims fine_dims,
+                                    const int32_t brick_size[3], const int32_t grid_offset[3],
+                                    double lo_thr, double hi_thr, rw_brick* bricks_out,
+                                    uint8_t* active_out, int32_t capacity, int32_t* n_candidates,
+                                    void* stream) {
+    if (n_seeds < 0 || (n_seeds > 0 && (!seed_index || !seed_label)))
+        return invalid("bad seed list");
+    return classify_impl(ctx, coarse_prob, coarse_dtype, coarse_dims, num_labels, factor, nullptr,
+                         seed_index, seed_label, n_seeds, fine_dims, brick_size, grid_offset,
+                         lo_thr, hi_thr, bricks_out, active_out, capacity, n_candidates, stream);
 }
 
 static rw_status check_subvolumes(const rw_brick* bricks, const rw_subvolume* sub, int n,

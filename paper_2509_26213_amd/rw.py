@@ -39,7 +39,7 @@ EXPORTS = [
     "rw_classify_bricks", "rw_bricks_workspace_bytes", "rw_solve_bricks", "rw_fill_bricks",
     "rw_backward_workspace_bytes", "rw_solve_backward", "rw_autotune", "rw_autotune_bricks",
     "rw_argmax", "rw_solve_noalloc", "rw_solve_noalloc_max_bytes", "rw_solve4d",
-    "rw_solve4d_workspace_bytes",
+    "rw_solve4d_workspace_bytes", "rw_classify_bricks_sparse", "rw_seed_edit_bricks",
 ]
 
 
@@ -157,6 +157,12 @@ def lib():
     L.rw_classify_bricks.argtypes = [P, P, I32, Dims, I32, I32, P, Dims, ctypes.POINTER(I32),
                                      ctypes.POINTER(I32), D, D, ctypes.POINTER(Brick), P, I32,
                                      ctypes.POINTER(I32), P]
+    L.rw_classify_bricks_sparse.argtypes = [P, P, I32, Dims, I32, I32, P, P, ctypes.c_int64, Dims,
+                                            ctypes.POINTER(I32), ctypes.POINTER(I32), D, D,
+                                            ctypes.POINTER(Brick), P, I32, ctypes.POINTER(I32), P]
+    L.rw_seed_edit_bricks.argtypes = [P, P, P, Dims, P, P, I32, Dims, I32, I32,
+                                      ctypes.POINTER(I32), ctypes.POINTER(I32), P,
+                                      ctypes.POINTER(D), I32, ctypes.POINTER(I32), P]
     L.rw_bricks_workspace_bytes.argtypes = [ctypes.POINTER(Brick), I32, I32, I32, I32]
     L.rw_bricks_workspace_bytes.restype = SZ
     L.rw_solve_bricks.argtypes = [P, ctypes.POINTER(Volume), ctypes.POINTER(Seeds), P, I32, Dims,
@@ -490,6 +496,58 @@ def classify_bricks(coarse_prob, labels, factor, brick=(64, 64, 64), offset=(0, 
     return [_from_brick(arr[i]) for i in range(n)], [bool(flags[i]) for i in range(n)]
 
 
+def classify_bricks_sparse(coarse_prob, seed_index, seed_label, fine_shape, factor,
+                           brick=(64, 64, 64), offset=(0, 0, 0), lo_thr=0.02, hi_thr=0.98,
+                           ctx=None):
+    """classify_bricks with the seeds given as a list: seed_index (device
+    int64, flat fine-grid indices) and seed_label (device uint8)."""
+    ctx = ctx or default_context()
+    K = int(coarse_prob.shape[0])
+    cd = _dims(coarse_prob.shape[1:])
+    fd = _dims(fine_shape)
+    if seed_index.dtype != torch.int64 or seed_label.dtype != torch.uint8:
+        raise ValueError("seed_index must be int64 and seed_label uint8")
+    if seed_index.numel() != seed_label.numel():
+        raise ValueError("seed_index and seed_label must have the same length")
+    si, sl = seed_index.contiguous(), seed_label.contiguous()
+    bs = (ctypes.c_int32 * 3)(int(brick[2]), int(brick[1]), int(brick[0]))
+    go = (ctypes.c_int32 * 3)(int(offset[2]), int(offset[1]), int(offset[0]))
+    ncand = ctypes.c_int32(0)
+    args = (ctx.handle, _ptr(coarse_prob), _dt_code(coarse_prob), cd, K, int(factor), _ptr(si),
+            _ptr(sl), int(si.numel()), fd, bs, go, float(lo_thr), float(hi_thr))
+    lib().rw_classify_bricks_sparse(*args, None, None, 0, ctypes.byref(ncand), _stream())
+    n = ncand.value
+    arr = (Brick * n)()
+    flags = (ctypes.c_uint8 * n)()
+    _check(lib().rw_classify_bricks_sparse(*args, arr, flags, n, ctypes.byref(ncand), _stream()),
+           "rw_classify_bricks_sparse")
+    return [_from_brick(arr[i]) for i in range(n)], [bool(flags[i]) for i in range(n)]
+
+
+def seed_edit_bricks(old_labels, new_labels, old_coarse, new_coarse, factor, brick=(64, 64, 64),
+                     offset=(0, 0, 0), ctx=None):
+    """Per candidate brick (the order of classify_bricks): whether a seed
+    edit reaches it (holds or borders a changed voxel) and how far the
+    coarse solution moved under it (rw_seed_edit_bricks)."""
+    ctx = ctx or default_context()
+    if old_coarse.dtype != new_coarse.dtype or old_coarse.shape != new_coarse.shape:
+        raise ValueError("old and new coarse probabilities must match in shape and type")
+    K = int(new_coarse.shape[0])
+    oc, nc = old_coarse.contiguous(), new_coarse.contiguous()
+    bs = (ctypes.c_int32 * 3)(int(brick[2]), int(brick[1]), int(brick[0]))
+    go = (ctypes.c_int32 * 3)(int(offset[2]), int(offset[1]), int(offset[0]))
+    ncand = ctypes.c_int32(0)
+    args = (ctx.handle, _ptr(old_labels), _ptr(new_labels), _dims(new_labels.shape), _ptr(oc),
+            _ptr(nc), _dt_code(nc), _dims(nc.shape[1:]), K, int(factor), bs, go)
+    lib().rw_seed_edit_bricks(*args, None, None, 0, ctypes.byref(ncand), _stream())
+    n = ncand.value
+    ed = (ctypes.c_uint8 * n)()
+    mv = (ctypes.c_double * n)()
+    _check(lib().rw_seed_edit_bricks(*args, ed, mv, n, ctypes.byref(ncand), _stream()),
+           "rw_seed_edit_bricks")
+    return [bool(ed[i]) for i in range(n)], [float(mv[i]) for i in range(n)]
+
+
 def _subvols_array(subvols, n):
     if subvols is None:
         return None
@@ -658,7 +716,6 @@ def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, pre
     a full re-solve by at most about change_tol: a brick's solution depends on
     its Dirichlet data through a maximum principle.  Returns (prob, info) with
     info["resolved"] / info["refilled"] the brick indices that were redone."""
-    import numpy as np
     ctx = ctx or default_context()
     V = make_volume(vol, lo, hi)
     g, lab = vol, new_labels
@@ -675,35 +732,11 @@ def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, pre
     if [tuple(map(tuple, b)) for b in cands] != [tuple(map(tuple, b)) for b in
                                                   prev_info["bricks"]]:
         raise ValueError("the brick grid differs from the previous solve's")
-    # bricks holding an edited voxel
-    edits = torch.nonzero(old_labels != new_labels).cpu().numpy()
-    cuts = []
-    for a in range(3):
-        starts = sorted({int(o[a]) for o, _ in cands})
-        cuts.append(np.array(starts))
-    n_axis = [len(c) for c in cuts]
-    edited = set()
-    dims = tuple(vol.shape)
-    steps = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))
-    for e in edits:
-        # the brick holding the voxel and the bricks whose shell it lies in
-        for d in steps:
-            p = [int(e[a]) + d[a] for a in range(3)]
-            if any(v < 0 or v >= n for v, n in zip(p, dims)):
-                continue
-            i = [int(np.searchsorted(cuts[a], p[a], side="right") - 1) for a in range(3)]
-            edited.add((i[0] * n_axis[1] + i[1]) * n_axis[2] + i[2])
-    # how far the coarse solution moved under each brick
-    dc = (coarse.double() - old_coarse.double()).abs().amax(0).cpu().numpy()
-    cshape = dc.shape
-    moved = []
-    for o, s in cands:
-        sl = tuple(slice(max(0, oo // f - 1), min(n, -(-(oo + ss) // f) + 1))
-                   for oo, ss, n in zip(o, s, cshape))
-        moved.append(float(dc[sl].max()))
+    edited, moved = seed_edit_bricks(old_labels, new_labels, old_coarse, coarse, f, brick,
+                                     offset, ctx=ctx)
     prob = prev_prob.clone()
     redo = [i for i in range(len(cands))
-            if i in edited or active[i] != prev_info["active"][i] or moved[i] > change_tol]
+            if edited[i] or active[i] != prev_info["active"][i] or moved[i] > change_tol]
     solve_ids = [i for i in redo if active[i]]
     fill_ids = [i for i in redo if not active[i]]
     if fill_ids:

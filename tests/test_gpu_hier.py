@@ -399,3 +399,74 @@ def test_persistent_brick_kernel_matches_oracle(rw, case, coarse_ref, monkeypatc
             sl = tuple(slice(a, a + b) for a, b in zip(o, s))
             err = np.max(np.abs(P[1:, sl[0], sl[1], sl[2]] - xb))
             assert err <= 1e-5, (o, s, err, it)
+
+
+@pytest.mark.parametrize("offset", [(0, 0, 0), (5, 3, 7)])
+def test_classify_with_seed_list_equals_dense_map(rw, case, coarse_ref, offset):
+    """Brick activity with the seed rule taken from a seed list (the form
+    the streamed pipeline uses, the fine label map never on the device)
+    equals the dense-map classification, brick for brick; a seed that
+    contradicts the coarse argmax makes its brick active."""
+    import torch
+    _, _, _, coarse = coarse_ref
+    brick = (16, 16, 16)
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, brick, offset)
+    flat = np.flatnonzero(case.labels)
+    sidx = torch.from_numpy(flat.astype(np.int64)).cuda()
+    slab = torch.from_numpy(case.labels.reshape(-1)[flat]).cuda()
+    c2, a2 = rw.classify_bricks_sparse(dev(coarse), sidx, slab, case.shape, 4, brick, offset)
+    assert c2 == cands and a2 == active
+    # no seeds at all: only the probability rule
+    _, a0 = rw.classify_bricks_sparse(dev(coarse), sidx[:0], slab[:0], case.shape, 4, brick,
+                                      offset)
+    nolab = np.zeros_like(case.labels)
+    _, ad = rw.classify_bricks(dev(coarse), dev(nolab), 4, brick, offset)
+    assert a0 == ad
+    # a seed against the argmax in an otherwise certain brick
+    certain = [i for i, a in enumerate(ad) if not a]
+    if certain:
+        o, s = cands[certain[0]]
+        P = np.stack([O.upsample_trilinear(coarse[k], case.shape, 4, (tuple(o), tuple(s)))
+                      for k in range(3)])
+        am = int(np.argmax(P[:, 0, 0, 0])) + 1
+        idx = (o[0] * case.shape[1] + o[1]) * case.shape[2] + o[2]
+        _, a1 = rw.classify_bricks_sparse(dev(coarse), torch.tensor([idx], device="cuda"),
+                                          torch.tensor([am % 3 + 1], dtype=torch.uint8,
+                                                       device="cuda"), case.shape, 4, brick,
+                                          offset)
+        assert a1[certain[0]] and sum(a1) == sum(ad) + 1
+
+
+def test_seed_edit_bricks_match_a_direct_count(rw, case, coarse_ref):
+    """rw_seed_edit_bricks against a direct numpy count on the host: the
+    bricks holding a changed voxel or one of its face neighbours, and the
+    largest coarse change over each brick's footprint and one cell around."""
+    import torch
+    _, _, _, coarse = coarse_ref
+    brick, offset = (16, 16, 16), (5, 3, 7)
+    new = case.labels.copy()
+    new[30:33, 20:23, 40:43][new[30:33, 20:23, 40:43] == 0] = 3
+    new[0, 0, 0] = 2
+    new[44, 51, 69] = 1
+    rng = np.random.default_rng(3)
+    coarse2 = coarse + 1e-3 * rng.standard_normal(coarse.shape) * (rng.random(coarse.shape) < 0.01)
+    ed, mv = rw.seed_edit_bricks(dev(case.labels), dev(new), dev(coarse), dev(coarse2), 4, brick,
+                                 offset)
+    grid = O.brick_grid(case.shape, brick, offset)
+    assert len(ed) == len(mv) == len(grid)
+    changed = np.argwhere(case.labels != new)
+    want = np.zeros(len(grid), bool)
+    for i, (o, s) in enumerate(grid):
+        o_, e_ = np.array(o), np.array(o) + np.array(s)
+        for p in changed:
+            outside = int(np.sum((p < o_) | (p >= e_)))       # axes on which p leaves the box
+            near = bool(np.all((p >= o_ - 1) & (p <= e_)))    # within one voxel of it
+            if outside == 0 or (outside == 1 and near):       # in the brick or its face shell
+                want[i] = True
+                break
+    assert ed == list(want)
+    dc = np.abs(coarse2 - coarse).max(0)
+    for i, (o, s) in enumerate(grid):
+        sl = tuple(slice(max(0, a // 4 - 1), min(n, -(-(a + b) // 4) + 1))
+                   for a, b, n in zip(o, s, dc.shape))
+        assert mv[i] == float(dc[sl].max()), i
