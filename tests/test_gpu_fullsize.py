@@ -104,8 +104,8 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     counts, two clipped border bricks, two others) equal the oracle's solves
     of those bricks, which start from the oracle's own float64 levels and its
     own float64 coarse solution (labels 2 and 3; label 1 as their
-    complement).  Both sides stop at relative residual 1e-8, so the
-    comparison is not limited by the stopping rule."""
+    complement), brick solves by the C oracle.  Both sides stop at relative
+    residual 1e-8, so the comparison is not limited by the stopping rule."""
     import torch
     from oracle import c_oracle, rw_oracle as O
     tol = 1e-8
@@ -136,16 +136,13 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     coarse = np.stack([c_oracle.solve_box(g2, l2, s, c.beta, tol=tol)[0] for s in (2, 3)])
     for i in pick:
         o, s = (tuple(v) for v in act[i])
-        lo = tuple(max(a - 1, 0) for a in o)
-        size = tuple(min(a + b + 1, n) - l for a, b, n, l in zip(o, s, c.shape, lo))
-        up = np.stack([O.upsample_trilinear(coarse[k], c.shape, 4, (lo, size)) for k in range(2)])
-
-        def shell_value(lab, zz, yy, xx, up=up, lo=lo):
-            return up[lab - 2][zz - lo[0], yy - lo[1], xx - lo[2]]
-
-        x0 = up[:, o[0] - lo[0]:o[0] - lo[0] + s[0], o[1] - lo[1]:o[1] - lo[1] + s[1],
-                o[2] - lo[2]:o[2] - lo[2] + s[2]]
-        xb, _ = O.solve_brick(g, c.labels, o, s, shell_value, x0, c.beta, tol=tol,
-                              solve_labels=[2, 3])
+        # upsampled coarse values over the brick and its one-voxel frame
+        # (frame voxels outside the volume are ignored by the solve)
+        frame = np.stack([O.upsample_trilinear(coarse[k], c.shape, 4,
+                                               (tuple(a - 1 for a in o), tuple(b + 2 for b in s)))
+                          for k in range(2)])
+        xb = np.stack([c_oracle.solve_box(g, c.labels, lab, c.beta, tol=tol, box=(o, s),
+                                          shell=frame[k], x0=frame[k][1:-1, 1:-1, 1:-1])[0]
+                       for k, lab in enumerate((2, 3))])
         ref = np.concatenate([1.0 - xb.sum(0, keepdims=True), xb])
         assert_parity(gpu[i], ref, what=f"brick {o} {s} ({its[i]} GPU iterations)")
