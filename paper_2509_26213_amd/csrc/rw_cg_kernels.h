@@ -77,8 +77,7 @@ struct WholeTiles {
         b.tw = 64 * tm.vx;
         b.X0 = tx * b.tw;
         b.Y0 = ty * tm.by;
-        b.z0 = tz * tm.zc;
-        b.z1 = min(b.z0 + tm.zc, G.nz);
+        tm.planes(tz, G.nz, b.z0, b.z1);
         b.vbase = 0;
         b.vstride = G.n;
         b.sidx = 0;

@@ -37,6 +37,7 @@ struct TileChoice {
     int brick_xcd = 0;  // brick solves: XCD-aware order of the tile worklist
     int persist = 0;    // brick solves: one persistent launch (one block per brick)
     int tuned = 0;      // 1: from the autotuner's table
+    int series = 1;     // time series: step-interleaved order (RW_SERIES_PLAIN=1: off)
 };
 // Reads the autotuner's table file once per process (rw_context_create).
 void load_tuning();
@@ -118,16 +119,44 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 
 // Tile order of the 2.5D stencil kernels: tiles of 64 x BY columns by zc
 // planes, tx fastest, then ty, then tz.  With xcd = 1 the grid has 8 * per
-// blocks and block b takes tile (b % 8) * per + b / 8: the hardware deals
+// blocks and block b takes slot (b % 8) * per + b / 8: the hardware deals
 // blocks to the eight XCDs round-robin, so each XCD walks one contiguous
-// range of tiles and the neighbour rows a tile re-reads were fetched into
+// range of slots and the neighbour rows a tile re-reads were fetched into
 // the same XCD's L2 by the tile before it.
+//
+// Volume time series (nt > 0): the planes are nt steps of nzs, each step cut
+// into cz chunks of at most zc planes (no chunk straddles two steps; tz =
+// step * cz + chunk), and slot j holds step j % nt of column and chunk j / nt:
+// the tiles of one column and chunk in consecutive steps, whose own planes
+// are each other's time neighbours, are neighbours in the slot order and so
+// run side by side in one XCD.  Slot -> tile is a bijection; a tile's
+// partial slot is its tile index, so the order changes no reduction.
 struct TileMap {
     int gx, gy, gz, zc, tiles, per, xcd, by, vx;
-    __device__ __forceinline__ int tile(int b) const {
-        if (!xcd) return b < tiles ? b : -1;
-        const int t = (b & 7) * per + (b >> 3);
-        return t < tiles ? t : -1;
+    int nt, nzs, cz;  // time series order (nt = 0: plain volume)
+    __host__ __device__ __forceinline__ int tile(int b) const {
+        int j;
+        if (!xcd) {
+            j = b < tiles ? b : -1;
+        } else {
+            j = (b & 7) * per + (b >> 3);
+            if (j >= tiles) j = -1;
+        }
+        if (j < 0 || nt == 0) return j;
+        const int s = j % nt, k = j / nt;
+        const int tx = k % gx, ty = (k / gx) % gy, c = k / (gx * gy);
+        return ((s * cz + c) * gy + ty) * gx + tx;
+    }
+    // first and one-past-last plane of tile layer tz
+    __host__ __device__ __forceinline__ void planes(int tz, int nz, int& z0, int& z1) const {
+        if (nt == 0) {
+            z0 = tz * zc;
+            z1 = z0 + zc < nz ? z0 + zc : nz;
+            return;
+        }
+        const int s = tz / cz, c = tz - s * cz;
+        z0 = s * nzs + c * zc;
+        z1 = z0 + zc < (s + 1) * nzs ? z0 + zc : (s + 1) * nzs;
     }
     __host__ __device__ int blocks() const { return xcd ? 8 * per : tiles; }
 };
@@ -143,7 +172,34 @@ inline TileMap make_tilemap(const Geom& G, int by, int zc, int xcd, int vx = 1) 
     m.tiles = m.gx * m.gy * m.gz;
     m.per = (m.tiles + 7) / 8;
     m.xcd = xcd;
+    m.nt = m.nzs = m.cz = 0;
     return m;
+}
+
+// Time-series order for nt steps of nzs planes (G.nz = nt * nzs), XCD-aware:
+// chunks of at most 64 planes, equal within a step, halved while the grid
+// has fewer than 1024 tiles (down to 4 planes).  Returns false (m untouched)
+// if the tiles would outnumber max_tiles, the partial slots a solve's
+// workspace holds.
+inline bool make_tilemap_series(const Geom& G, int by, int vx, int nt, int nzs, int max_tiles,
+                                TileMap& m) {
+    if (nt < 2 || nzs < 1 || (int64_t)nt * nzs != G.nz) return false;
+    TileMap t = make_tilemap(G, by, 4, 1, vx);
+    const int64_t cols = (int64_t)t.gx * t.gy;
+    int zc = (nzs + ((nzs + 63) / 64) - 1) / ((nzs + 63) / 64);
+    while (zc > 4 && cols * nt * ((nzs + zc - 1) / zc) < 1024) zc = std::max(4, zc / 2);
+    zc = std::max(4, zc);
+    t.zc = zc;
+    t.nt = nt;
+    t.nzs = nzs;
+    t.cz = (nzs + zc - 1) / zc;
+    const int64_t tiles = cols * nt * t.cz;
+    if (tiles > max_tiles) return false;
+    t.gz = nt * t.cz;
+    t.tiles = int(tiles);
+    t.per = (t.tiles + 7) / 8;
+    m = t;
+    return true;
 }
 
 }  // namespace rw

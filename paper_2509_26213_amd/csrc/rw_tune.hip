@@ -167,6 +167,7 @@ TileChoice tuned_tiles(const Geom& G, int precision, int R) {
         c.tuned = 0;
     }
     if (c.zc < 4) c.zc = 4;
+    c.series = env_set("RW_SERIES_PLAIN") ? 0 : 1;
     return c;
 }
 

@@ -566,6 +566,11 @@ inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8
     S.G.tz = tz;
     S.wc = make_wcoef(vol, o->beta, o->w_eps);
     S.tm = make_tilemap(S.G, BY, tc.zc, tc.xcd, VX);
+    // a time series takes the step-interleaved XCD-aware order when its
+    // tiles fit the workspace's partial slots (RW_SERIES_PLAIN=1: the plain
+    // volume order, for comparison)
+    if (T4 && tz > 0 && S.G.nz / tz > 1 && tc.series)
+        make_tilemap_series(S.G, BY, VX, int(S.G.nz / tz), tz, max_tiles(S.G), S.tm);
     S.lab0 = lab0;
     S.mixed = o->precision == RW_PREC_MIXED;
     S.reliable = S.mixed && o->refine_mode == 0;
