@@ -89,7 +89,11 @@ def kernel_source_hash():
 
 def tile_key(tile):
     """Canonical text of a stencil tile shape (the stats' tile dict)."""
-    return "vx={vx} by={by} zc={zc} xcd={xcd}".format(**tile)
+    key = "vx={vx} by={by} zc={zc} xcd={xcd}".format(**tile)
+    by2, zc2 = tile.get("by2", tile["by"]), tile.get("zc2", tile["zc"])
+    if by2 in (0, tile["by"]) and zc2 in (0, tile["zc"]):
+        return key
+    return key + f" pass2 by={by2} zc={zc2}"
 
 
 def measured_traffic(kernel, workload, tile):

@@ -143,6 +143,9 @@ typedef struct {
                                             launch (0: one launch per CG pass) */
     int32_t tile_tuned;                  /* 1: the tile shape came from the autotuner's
                                             table (librw.tune), 0: the built-in default */
+    int32_t tile_by2, tile_zc2;          /* rows and planes of CG pass 2's tiles (whole
+                                            volumes may run pass 2 on other tiles than
+                                            pass 1) */
 } rw_stats;
 
 /* Fine-level brick: origin and size in voxels of the fine grid (or of its

@@ -989,6 +989,8 @@ rw_status bricks_run(rw_context* ctx, const rw_volume* fine, const rw_seeds* see
         stats->unknowns = P.vox;
         stats->refinements = int32_t(std::min<int64_t>(refreshes, INT32_MAX));
         stats->tile_by = BY;
+        stats->tile_by2 = BY;
+        stats->tile_zc2 = tc.zc;
         stats->tile_zc = tc.zc;
         stats->tile_vx = BVX;
         stats->tile_xcd = tc.brick_xcd;

@@ -38,6 +38,8 @@ struct TileChoice {
     int persist = 0;    // brick solves: one persistent launch (one block per brick)
     int tuned = 0;      // 1: from the autotuner's table
     int series = 1;     // time series: step-interleaved order (RW_SERIES_PLAIN=1: off)
+    int by2 = 0;        // whole volumes: rows of pass 2's tiles (0 or by: pass 1's)
+    int zc2 = 0;        // whole volumes: planes of pass 2's tiles (0: zc)
 };
 // Reads the autotuner's table file once per process (rw_context_create).
 void load_tuning();

@@ -35,6 +35,11 @@ rw_status run_group(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
             return run_group_vx<V, T, R, 4, 4, T4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out,
                                                    stats, r_base, worst, tz);
     }
+    if constexpr (std::is_same<T, float>::value) {
+        if (tc.vx == 2 && tc.by == 8 && tc.by2 == 4)
+            return run_group_vx<V, T, R, 2, 8, T4, 4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out,
+                                                      stats, r_base, worst, tz);
+    }
     if (tc.vx == 2 && tc.by == 8)
         return run_group_vx<V, T, R, 2, 8, T4>(ctx, vol, lab, o, lab0, x0, B, tc, prob_out,
                                                stats, r_base, worst, tz);

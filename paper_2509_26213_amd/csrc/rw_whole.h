@@ -246,6 +246,12 @@ __global__ __launch_bounds__(256) void k_finish(const uint8_t* __restrict__ lab,
 inline TileChoice choose_tiles(const Geom& G, int precision, int R) {
     TileChoice c = tuned_tiles(G, precision, R);
     c.by = c.by == 8 && c.vx == 2 ? 8 : 4;
+    // pass 2 on 4-row tiles beside 8-row pass-1 tiles (float32 only), else
+    // the same tiles
+    if (!(c.by == 8 && c.by2 == 4 && precision == RW_PREC_MIXED)) {
+        c.by2 = c.by;
+        c.zc2 = 0;
+    }
     if (c.vx != 2 && c.vx != 4) c.vx = 1;
     if (precision != RW_PREC_MIXED && c.vx > 2) c.vx = 2;
     const int64_t cols =
@@ -253,6 +259,11 @@ inline TileChoice choose_tiles(const Geom& G, int precision, int R) {
     while (c.zc > 4 && cols * ((G.nz + c.zc - 1) / c.zc) < 1024) c.zc = std::max(4, c.zc / 2);
     // the partial buffers are sized for 64 x 4 x 4 tiles
     c.zc = std::max(4, c.zc);
+    if (c.zc2 <= 0) c.zc2 = c.zc;
+    const int64_t cols2 =
+        (int64_t)((G.nx + 64 * c.vx - 1) / (64 * c.vx)) * ((G.ny + c.by2 - 1) / c.by2);
+    while (c.zc2 > 4 && cols2 * ((G.nz + c.zc2 - 1) / c.zc2) < 1024) c.zc2 = std::max(4, c.zc2 / 2);
+    c.zc2 = std::max(4, c.zc2);
     return c;
 }
 
@@ -292,10 +303,13 @@ struct PlaneBatch {
     static constexpr int value = per / VX > 0 ? per / VX : 1;
 };
 
-// T4: the grid is a volume time series (G.tz planes per time step).
-template <typename V, typename T, int R, int VX, int BY_ = 4, bool T4 = false>
+// T4: the grid is a volume time series (G.tz planes per time step).  BY2:
+// rows of pass 2's tiles (tm2), which may differ from pass 1's (tm): pass 2
+// forms nothing on the halo, so it keeps its own best shape.
+template <typename V, typename T, int R, int VX, int BY_ = 4, bool T4 = false, int BY2_ = BY_>
 struct WholeSolve {
     static constexpr int BY = BY_;
+    static constexpr int BY2 = BY2_;
     static constexpr int ZU = PlaneBatch<T, VX>::value;
     rw_context* ctx;
     const V* vol;
@@ -303,6 +317,7 @@ struct WholeSolve {
     Geom G;
     WCoef wc;
     TileMap tm;
+    TileMap tm2{};  // pass 2 (tiles == 0: the same as tm)
     int lab0;
     bool mixed;
     bool reliable;
@@ -329,19 +344,30 @@ struct WholeSolve {
         return w;
     }
     dim3 block() const { return dim3(64, BY); }
+    const TileMap& map2() const { return tm2.tiles ? tm2 : tm; }
+    dim3 grid2() const { return dim3(unsigned(map2().blocks())); }
+    WholeTiles ts2() const {
+        WholeTiles w;
+        w.tm = map2();
+        w.G = G;
+        w.ntiles = map2().tiles;
+        return w;
+    }
+    dim3 block2() const { return dim3(64, BY2); }
 
     rw_status launch_iteration(hipEvent_t* ev) {
         hipStream_t s = ctx->s;
+        if (map2().by != BY2) return invalid("pass-2 tile map does not match its block shape");
         if (ev) RW_HIP(hipEventRecord(ev[0], s));
         hipLaunchKernelGGL((k_cg_pass1<V, T, R, BY, ZU, VX, WholeTiles, false, T4>), grid(), block(), 0, s, vol, wc, ts(), zv,
                            p0, p1, (T*)nullptr, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_fin1<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st);
         if (ev) RW_HIP(hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY, ZU, VX, WholeTiles, false, T4>), grid(), block(), 0, s, vol, lab, wc, ts(),
+        hipLaunchKernelGGL((k_cg_pass2<V, T, R, BY2, ZU, VX, WholeTiles, false, T4>), grid2(), block2(), 0, s, vol, lab, wc, ts2(),
                            xv, zv, (const T*)p0, (const T*)p1, B.st, B.part);
         if (ev) RW_HIP(hipEventRecord(ev[3], s));
-        hipLaunchKernelGGL((k_fin2<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, tm.tiles, B.st,
+        hipLaunchKernelGGL((k_fin2<R>), dim3(1), dim3(FIN_THREADS), 0, s, B.part, map2().tiles, B.st,
                            mixed ? 0 : 1);
         RW_HIP(hipGetLastError());
         return RW_OK;
@@ -553,12 +579,12 @@ struct WholeSolve {
     }
 };
 
-template <typename V, typename T, int R, int VX, int BY = 4, bool T4 = false>
+template <typename V, typename T, int R, int VX, int BY = 4, bool T4 = false, int BY2 = BY>
 inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8_t* lab,
                               const rw_options* o, int lab0, const double* x0,
                               const GroupBuffers& B, const TileChoice& tc, void* prob_out,
                               rw_stats* stats, int r_base, int* worst, int tz = 0) {
-    WholeSolve<V, T, R, VX, BY, T4> S;
+    WholeSolve<V, T, R, VX, BY, T4, BY2> S;
     S.ctx = ctx;
     S.vol = static_cast<const V*>(vol->data);
     S.lab = lab;
@@ -571,6 +597,7 @@ inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8
     // volume order, for comparison)
     if (T4 && tz > 0 && S.G.nz / tz > 1 && tc.series)
         make_tilemap_series(S.G, BY, VX, int(S.G.nz / tz), tz, max_tiles(S.G), S.tm);
+    if (BY2 != BY) S.tm2 = make_tilemap(S.G, BY2, tc.zc2, tc.xcd, VX);
     S.lab0 = lab0;
     S.mixed = o->precision == RW_PREC_MIXED;
     S.reliable = S.mixed && o->refine_mode == 0;
@@ -612,6 +639,8 @@ inline rw_status run_group_vx(rw_context* ctx, const rw_volume* vol, const uint8
         stats->rhs_voxel_iterations += S.rhs_vox;
         stats->refinements += S.refreshes();
         stats->tile_by = S.tm.by;
+        stats->tile_by2 = S.map2().by;
+        stats->tile_zc2 = S.map2().zc;
         stats->tile_zc = S.tm.zc;
         stats->tile_vx = VX;
         stats->tile_xcd = S.tm.xcd;

@@ -84,7 +84,8 @@ class Stats(ctypes.Structure):
                 ("rhs_voxel_iterations", ctypes.c_int64), ("active_bricks", ctypes.c_int64),
                 ("unknowns", ctypes.c_int64), ("tile_vx", ctypes.c_int32),
                 ("tile_xcd", ctypes.c_int32), ("brick_blocks", ctypes.c_int32),
-                ("tile_tuned", ctypes.c_int32)]
+                ("tile_tuned", ctypes.c_int32), ("tile_by2", ctypes.c_int32),
+                ("tile_zc2", ctypes.c_int32)]
 
     def to_dict(self):
         R = self.num_solved
@@ -92,7 +93,7 @@ class Stats(ctypes.Structure):
                     rel_residual=list(self.rel_residual[:R]), num_solved=R,
                     refinements=self.refinements,
                     tile=dict(vx=self.tile_vx, by=self.tile_by, zc=self.tile_zc,
-                              xcd=self.tile_xcd),
+                              xcd=self.tile_xcd, by2=self.tile_by2, zc2=self.tile_zc2),
                     tile_tuned=bool(self.tile_tuned),
                     device_ms=self.device_ms,
                     loop_ms=self.loop_ms, pass_ms=list(self.pass_ms),

@@ -123,3 +123,22 @@ def test_bad_time_steps_are_refused(rw):
     prob, _ = rw.solve4d(vol, lab, 2, 1.0, tol=1e-10, lo=0.0, hi=1.0)
     # constant image: x_fg is harmonic with unit weights; spot-check the seeds
     assert float(prob[1, 1, 2, 3, 4]) == 1.0 and float(prob[1, 0, 0, 0, 0]) == 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_series_and_plain_tile_orders_agree(rw, precision, monkeypatch):
+    """The time-series tile order (chunks within one time step, steps
+    interleaved) and the plain volume order (chunks straddling steps) solve
+    the same system: equal within the tol-1e-10 gap.  Here both take
+    4-plane chunks: [0, 4), [4, 8), [8, 9) of every step against chunks
+    that straddle each step boundary, so the partial sums differ."""
+    vol, lab, beta = _random4d((6, 9, 13, 140), 3, 12, 25.0, seed=74)
+    p_s, a_s, st_s = rw.solve4d(dev(vol), dev(lab), 3, beta, tol=1e-10, precision=precision,
+                                return_stats=True)
+    monkeypatch.setenv("RW_SERIES_PLAIN", "1")
+    p_p, a_p, st_p = rw.solve4d(dev(vol), dev(lab), 3, beta, tol=1e-10, precision=precision,
+                                return_stats=True)
+    assert st_s["status"] == 0 and st_p["status"] == 0
+    assert st_s["tile"]["zc"] == 4 and st_p["tile"]["zc"] == 4
+    bound = 1e-8 if precision == "fp64" else 2e-6
+    assert np.max(np.abs(host(p_s) - host(p_p))) <= bound

@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 # eight waves) by 64 planes, plain order.  On a 256^3 volume the library
 # shortens the tiles to 16 planes so that a launch still has 1024 tiles; the
 # kernel (its columns, waves and loads) is the benchmark's.
-BENCH_TILE = {"RW_TILE_VX": "2", "RW_TILE_BY": "8", "RW_TILE_ZC": "64", "RW_TILE_XCD": "0"}
+BENCH_TILE = {"RW_TILE_VX": "2", "RW_TILE_BY": "8", "RW_TILE_ZC": "64", "RW_TILE_XCD": "0",
+              "RW_TILE_BY2": "4", "RW_TILE_ZC2": "32"}
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +62,10 @@ def test_blob256_bench_tile_matches_oracle(rw, blob256, monkeypatch, precision):
     prob, am, st = rw.solve(dev(c.vol), dev(c.labels), 3, c.beta, tol=1e-10, precision=precision,
                             return_stats=True)
     assert st["status"] == 0
-    assert st["tile"] == dict(vx=2, by=8, zc=16, xcd=0), st["tile"]
+    # pass 1 on 128 x 8 x 16 (the fill rule halves 64 at 256^3); mixed runs
+    # pass 2 on 128 x 4 x 32 as the 512^3 benchmark does, float64 on pass 1's
+    split = dict(by2=4, zc2=32) if precision == "mixed" else dict(by2=8, zc2=16)
+    assert st["tile"] == dict(vx=2, by=8, zc=16, xcd=0, **split), st["tile"]
     P = host(prob)
     err, ties = assert_parity(P, ref, what=f"blob256 {precision}")
     print(f"blob256 {precision}: max-abs {err:.2e}, {ties} near-ties, iters {st['iters']} vs "

@@ -182,6 +182,33 @@ def test_tile_shapes_agree(rw, monkeypatch, vx, by, zc, xcd, shape):
         assert_parity(host(prob), ref, what=f"tile vx {vx} by {by} zc {zc} {precision}")
 
 
+@pytest.mark.parametrize("zc, zc2, shape", [(64, 32, (29, 70, 131)), (16, 5, (20, 33, 45)),
+                                          (8, 64, (9, 5, 300))])
+def test_pass2_on_its_own_tiles(rw, monkeypatch, zc, zc2, shape):
+    """Mixed precision runs pass 2 on 128 x 4 x zc2 tiles beside pass 1's
+    128 x 8 x zc (the 512^3 default): the oracle's solution, and within the
+    stopping rule's gap of the same solve on pass 1's tiles (the partial sums
+    of r.z and r.r are grouped by other tiles)."""
+    c = blob_case(shape=shape, n_blobs=5, K=3, seeds_per_label=30, sigma=0.08,
+                  rmin=4, rmax=12, seed=13)
+    ref, _ = _oracle_same(c, tol=1e-11)
+    vol, lab = _case_tensors(c)
+    for k, v in (("RW_TILE_VX", 2), ("RW_TILE_BY", 8), ("RW_TILE_ZC", zc), ("RW_TILE_XCD", 0)):
+        monkeypatch.setenv(k, str(v))
+    same, _, st1 = rw.solve(vol, lab, 3, c.beta, tol=1e-9, precision="mixed", return_stats=True)
+    assert st1["tile"]["by2"] == 8
+    monkeypatch.setenv("RW_TILE_BY2", "4")
+    monkeypatch.setenv("RW_TILE_ZC2", str(zc2))
+    prob, _, st = rw.solve(vol, lab, 3, c.beta, tol=1e-9, precision="mixed", return_stats=True)
+    assert st["status"] == 0 and st["tile"]["by"] == 8 and st["tile"]["by2"] == 4
+    assert st["tile"]["zc2"] <= max(zc2, 4)
+    assert_parity(host(prob), ref, what=f"pass 2 on 128 x 4 x {zc2}")
+    assert np.max(np.abs(host(prob) - host(same))) <= 1e-6
+    # float64 keeps one tile shape for both passes
+    _, _, s64 = rw.solve(vol, lab, 3, c.beta, tol=1e-9, precision="fp64", return_stats=True)
+    assert s64["tile"]["by2"] == s64["tile"]["by"]
+
+
 def test_graph_and_plain_launches_bitwise_equal(rw):
     c = random_case((21, 30, 65), K=3, seeds_per_label=30, beta=40.0, seed=2)
     vol, lab = _case_tensors(c)
@@ -352,7 +379,8 @@ def test_tile_table_file_is_written_and_read_by_later_processes(tmp_path):
     assert second.returncode == 0, second.stderr[-2000:]
     r2 = json.loads(second.stdout.strip().splitlines()[-1])
     vx, zc, xcd, by = r1["best"]
-    assert r2["tuned"] and r2["tile"] == dict(vx=vx, by=by, zc=r2["tile"]["zc"], xcd=xcd)
+    t2 = r2["tile"]
+    assert r2["tuned"] and (t2["vx"], t2["by"], t2["xcd"]) == (vx, by, xcd)
     off = subprocess.run([sys.executable, "-c", code, "solve"],
                          env=dict(os.environ, RW_TUNE_FILE=""), capture_output=True, text=True,
                          timeout=600)
