@@ -109,6 +109,12 @@ typedef struct {
                              float64 for the solved labels (NULL = 0); rw_solve_bricks:
                              [K][fine voxels] float32 as prob_out (NULL = upsampled
                              coarse).  Read on unseeded voxels. */
+    int64_t brick_voxels; /* rw_solve_bricks, rw_autotune_bricks: voxels of the
+                             level's nominal (unclipped) brick, the key of the tile
+                             table, so that a batch of clipped border bricks (a
+                             region of interest, a seed edit) runs on the same
+                             tiles, and so the same reduction order, as the whole
+                             level; 0 = the largest brick of the batch */
 } rw_options;
 
 /* Statistics of one call (host memory). */

@@ -1005,7 +1005,8 @@ template <typename V, typename T, int R>
 rw_status bricks_by(rw_context* ctx, const rw_volume* fine, const rw_seeds* seeds,
                            const Shell& sh, const rw_brick* bricks, const rw_subvolume* sub, int n,
                            const rw_options* o, float* prob, int32_t* it, void* ws, rw_stats* st) {
-    const TileChoice tc = brick_tiles(o->precision, R, max_brick_voxels(bricks, n));
+    const TileChoice tc = brick_tiles(
+        o->precision, R, o->brick_voxels > 0 ? o->brick_voxels : max_brick_voxels(bricks, n));
     if (tc.vx == 2) {
         if (tc.by == 8)
             return bricks_run<V, T, R, 8, 2>(ctx, fine, seeds, sh, bricks, sub, n, o, prob, it, ws,

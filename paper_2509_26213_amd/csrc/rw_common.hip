@@ -300,6 +300,7 @@ void rw_default_options(rw_options* o) {
     o->use_graph = 1;
     o->kernel_timing = 0;
     o->x0 = nullptr;
+    o->brick_voxels = 0;
 }
 
 rw_status rw_context_create(rw_context** out) {

@@ -319,6 +319,7 @@ rw_status rw_autotune_bricks(rw_context* ctx, const rw_volume* fine, const rw_se
     int64_t max_vox = 0;
     for (int i = 0; i < n_bricks; ++i)
         max_vox = std::max<int64_t>(max_vox, (int64_t)bricks[i].sx * bricks[i].sy * bricks[i].sz);
+    if (opts->brick_voxels > 0) max_vox = opts->brick_voxels;
     rw_options o = *opts;
     o.kernel_timing = 1;
     o.max_iter = std::max(2, o.check_interval) * 2;

@@ -69,7 +69,7 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("solve_all_labels", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("kernel_timing", ctypes.c_int32), ("refine_mode", ctypes.c_int32),
-                ("x0", ctypes.c_void_p)]
+                ("x0", ctypes.c_void_p), ("brick_voxels", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -327,7 +327,7 @@ def apply_operator(vol, labels, p, beta, precision="fp64", w_eps=0.0, lo=None, h
 
 def options(beta, tol=1e-6, precision="fp64", max_iter=20000, max_refine=5, inner_tol=1e-3,
             solve_all_labels=False, check_interval=16, use_graph=True, kernel_timing=False,
-            w_eps=0.0, x0=None, refine_mode="reliable", update_delta=0.1):
+            w_eps=0.0, x0=None, refine_mode="reliable", update_delta=0.1, brick_voxels=0):
     o = Options()
     lib().rw_default_options(ctypes.byref(o))
     o.beta, o.tol, o.w_eps, o.inner_tol = float(beta), float(tol), float(w_eps), float(inner_tol)
@@ -341,6 +341,7 @@ def options(beta, tol=1e-6, precision="fp64", max_iter=20000, max_refine=5, inne
     o.update_delta = float(update_delta)
     o.x0 = _ptr(x0) if x0 is not None else None
     o._keep = x0
+    o.brick_voxels = int(brick_voxels)
     return o
 
 
@@ -693,7 +694,8 @@ def hierarchical_solve(vol, labels, K, beta, levels=2, brick=(64, 64, 64), offse
     if act:
         _, iters, bst = solve_bricks(vol, labels, K, beta, coarse, f, act, prob_out=prob, tol=tol,
                                      precision=brick_precision, lo=V.norm_lo, hi=V.norm_hi,
-                                     ctx=ctx, return_stats=True)
+                                     ctx=ctx, return_stats=True,
+                                     brick_voxels=int(brick[0]) * brick[1] * brick[2])
     if return_info:
         return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
                           evaluated=want, brick_iters=iters, brick_stats=bst)
@@ -747,7 +749,8 @@ def resolve_after_seed_edit(vol, old_labels, new_labels, K, beta, prev_prob, pre
         _, iters, bst = solve_bricks(vol, new_labels, K, beta, coarse, f,
                                      [cands[i] for i in solve_ids], prob_out=prob, tol=tol,
                                      precision=brick_precision, lo=V.norm_lo, hi=V.norm_hi,
-                                     ctx=ctx, return_stats=True, x0=prev_prob)
+                                     ctx=ctx, return_stats=True, x0=prev_prob,
+                                     brick_voxels=int(brick[0]) * brick[1] * brick[2])
     return prob, dict(coarse=coarse, coarse_stats=cst, bricks=cands, active=active,
                       resolved=solve_ids, refilled=fill_ids, brick_iters=iters, brick_stats=bst,
                       coarse_moved=moved)

@@ -304,7 +304,8 @@ def streamed_solve(vol_host, lab_host, K, beta, brick=(128, 128, 128), pool=16, 
         _, iters, bst = rw.solve_bricks(P["v"], P["l"], K, beta, coarse, f, bricks_local,
                                         prob_out=P["p"], tol=tol, precision=precision, lo=lo,
                                         hi=hi, ctx=ctx, return_stats=True, subvols=subs,
-                                        update_delta=update_delta)
+                                        update_delta=update_delta,
+                                        brick_voxels=int(brick[0]) * brick[1] * brick[2])
         solve_s += time.perf_counter() - ts
         iters_all += iters
         meta.append(bst)

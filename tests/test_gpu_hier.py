@@ -470,3 +470,48 @@ def test_seed_edit_bricks_match_a_direct_count(rw, case, coarse_ref):
         sl = tuple(slice(max(0, a // 4 - 1), min(n, -(-(a + b) // 4) + 1))
                    for a, b, n in zip(o, s, dc.shape))
         assert mv[i] == float(dc[sl].max()), i
+
+
+def test_region_of_interest_keeps_the_levels_tiles_after_tuning(tmp_path):
+    """With a tile-table entry for the level's 16^3 bricks, a region made
+    only of clipped border bricks still runs on that entry's tiles (the
+    pipeline passes the nominal brick size as the table key), so the box
+    holds the full solve bit for bit; the same bricks solved without the key
+    fall into a smaller size class and take the built-in tiles."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    table = tmp_path / "librw.tune"
+    table.write_text("brick 1 2 12 4 16 0 1 0 0\n")
+    code = """
+import json, sys, torch
+sys.path.insert(0, %r)
+from paper_2509_26213_amd import rw
+from synth import blob_case
+c = blob_case(shape=(45, 52, 70), n_blobs=6, K=3, seeds_per_label=40, sigma=0.06, rmin=5,
+              rmax=14, seed=31, dtype="u16")
+vol = torch.from_numpy(c.vol).cuda(); lab = torch.from_numpy(c.labels).cuda()
+kw = dict(levels=2, brick=(16, 16, 16), offset=(5, 3, 7), brick_precision="mixed", return_info=True)
+roi = ((0, 3), (0, 52), (0, 70))
+full, fi = rw.hierarchical_solve(vol, lab, 3, c.beta, **kw)
+part, pi = rw.hierarchical_solve(vol, lab, 3, c.beta, roi=roi, **kw)
+sl = tuple(slice(a, b) for a, b in roi)
+act = [b for b, a, e in zip(pi["bricks"], pi["active"], pi["evaluated"]) if a and e]
+_, _, st = rw.solve_bricks(vol, lab, 3, c.beta, pi["coarse"], 4, act, return_stats=True)
+print(json.dumps(dict(equal=bool(torch.equal(part[(slice(None),) + sl], full[(slice(None),) + sl])),
+                      n=len(act), biggest=max(s[0] * s[1] * s[2] for _, s in act),
+                      full=fi["brick_stats"]["tile"], roi=pi["brick_stats"]["tile"],
+                      unkeyed=st["tile"], tuned=[fi["brick_stats"]["tile_tuned"],
+                                                 st["tile_tuned"]])))
+""" % root
+    r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, RW_TUNE_FILE=str(table)),
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n"] > 0 and out["biggest"] < 4096, out
+    assert out["tuned"] == [True, False], out
+    assert out["full"] == out["roi"] and out["full"]["by"] == 4 and out["full"]["vx"] == 1, out
+    assert out["unkeyed"] != out["full"], out
+    assert out["equal"], out
