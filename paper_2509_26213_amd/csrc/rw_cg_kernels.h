@@ -883,9 +883,11 @@ struct XCell {
     bool dir;
 
     // lmask: the labels whose values are wanted (the others are left 0).
+    // shv (optional): the cell's shell values per label, interpolated
+    // beforehand (else interpolated here).
     __device__ __forceinline__ void make(double gv, uint8_t lb, const double (&xb)[R], bool in_vol,
                                          bool in_box, const Shell& sh, int lab0, int gx, int gy,
-                                         int gz, int lmask) {
+                                         int gz, int lmask, const double* shv = nullptr) {
         g = in_vol ? (GT)gv : GT(0);
         dir = !(in_box && lb == 0);
 #pragma unroll
@@ -894,7 +896,7 @@ struct XCell {
             if (!in_vol || !(lmask & (1 << r))) v = 0.0;
             else if (lb != 0) v = (lab0 > 0 && lb == lab0 + r) ? 1.0 : 0.0;
             else if (in_box) v = xb[r];
-            else if (sh.coarse && lab0 > 0) v = upsample(sh, lab0 + r, gx, gy, gz);
+            else if (sh.coarse && lab0 > 0) v = shv ? shv[r] : upsample(sh, lab0 + r, gx, gy, gz);
             xt[r] = v;
         }
     }
@@ -913,18 +915,24 @@ struct XCell {
 // by the lane that loads it and shared through LDS.  T4 (volume time series,
 // whole volume): the two time neighbours of an own cell, tz planes away, are
 // loaded and formed by its lane.
-template <typename V, int R, int BY, int VX, bool YM>
+// SHX (brick tiles): LDS slots for the x-halo shell cache, per wave, row
+// of the wave, side and plane of a batch of RES_HZ planes, and label.
+constexpr int RES_HZ = 32;
+template <typename V, int R, int BY, int VX, bool YM, bool SHX = false>
 struct ResidualSmem {
     using Lanes = TileLanes<BY, 1, VX, YM>;
     using GT = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
     static constexpr size_t cells = size_t(Lanes::TR + 2) * (Lanes::TC + 2);
-    static constexpr size_t bytes = (8 * R + sizeof(GT) + 1) * cells;
+    static constexpr size_t base = ((8 * R + sizeof(GT) + 1) * cells + 15) / 16 * 16;
+    static constexpr size_t shx = SHX ? sizeof(double) * BY * Lanes::HR * 2 * RES_HZ * R : 0;
+    static constexpr size_t bytes = base + shx;
 };
 
 // One tile of the float64 residual, accumulated into acc; false if a refresh
 // (mode 2) has no flagged label in the tile's box.  smem: at least
 // ResidualSmem<V, R, BY, VX, YM>::bytes of LDS.
-template <typename V, typename T, int R, int BY, int VX, bool YM = false, bool T4 = false>
+template <typename V, typename T, int R, int BY, int VX, bool YM = false, bool T4 = false,
+          bool SHX = false>
 __device__ __forceinline__ bool residual_tile(
     char* __restrict__ smem, const BoxTile& bt, const V* __restrict__ volp,
     const uint8_t* __restrict__ labp, WCoef wc, const Shell& sh, int lab0,
@@ -960,6 +968,41 @@ __device__ __forceinline__ bool residual_tile(
     Lanes L;
     L.init(G, bt);
     const int64_t bplane = (int64_t)bt.sx * bt.sy;
+
+    // SHX: the x-halo cells of a brick tile lie in the brick's Dirichlet
+    // shell, and every wave needs one interpolated coarse value per side and
+    // plane.  Formed on the plane loop's path these cost a dependent round of
+    // coarse loads per plane; instead every lane of the wave forms one
+    // (plane, side) entry per row for RES_HZ planes at a time, kept in the
+    // wave's own LDS slots, and the halo lanes read them.
+    constexpr int HRW = Lanes::HR;
+    double* shx = nullptr;
+    if constexpr (SHX)
+        shx = reinterpret_cast<double*>(smem + ResidualSmem<V, R, BY, VX, YM, true>::base);
+    auto fill_shx = [&](int lz0) {
+        const int k = L.lx >> 1, side = L.lx & 1;
+        const int lz = lz0 + k;
+        const int xl = side ? bt.X0 + Lanes::TC : bt.X0 - 1;
+        const int gxh = bt.ox + xl;
+#pragma unroll
+        for (int vr = 0; vr < HRW; ++vr) {
+            const int yl = bt.Y0 + L.ly + (YM ? BY * vr : 0);
+            const int gyh = bt.oy + yl;
+            const bool shell = sh.coarse && lab0 > 0 && lz < bt.z1 && gxh >= 0 && gxh < G.nx &&
+                               gyh < G.ny && !(xl >= 0 && xl < bt.sx && yl < bt.sy);
+            double* e = shx + ((((size_t)L.ly * HRW + vr) * 2 + side) * RES_HZ + k) * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                e[r] = shell && (lmask & (1 << r))
+                           ? upsample(sh, lab0 + r, bt.gox + gxh, bt.goy + gyh, bt.goz + bt.oz + lz)
+                           : 0.0;
+        }
+    };
+    // this lane's x-halo entry (side, row) in the cache
+    const double* shx_lane = nullptr;
+    if constexpr (SHX)
+        shx_lane = shx + (((size_t)L.ly * HRW + min(L.lx >> 1, HRW - 1)) * 2 + (L.lx & 1)) *
+                             RES_HZ * R;
 
     // Raw values of a cell (intensity, label, float64 iterates); loads
     // are issued one plane (halo cells) or two planes (own cells) ahead of
@@ -1021,9 +1064,18 @@ __device__ __forceinline__ bool residual_tile(
         load_halo(lz + 1, hx1, hy1);
         // (B) cells of plane lz+1 (own) and of plane lz's halo
         make_own(lz + 1, own1, cp, lbp);
+        const double* shv = nullptr;
+        if constexpr (SHX) {
+            const int kz = (lz - bt.z0) % RES_HZ;
+            if (kz == 0) {
+                fill_shx(lz);
+                __syncthreads();
+            }
+            shv = shx_lane + (size_t)kz * R;
+        }
         XCell<GT, R> hx;
         hx.make((double)hx0.g, hx0.lb, hx0.xb, L.hx_vol && zvol, L.hx_box && inb, sh, lab0,
-                bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz, lmask);
+                bt.gox + L.hx_gx, bt.goy + L.hx_gy, bt.goz + gz, lmask, shv);
         XCell<GT, R> hy[NYH][HV];
 #pragma unroll
         for (int j = 0; j < NYH; ++j)
@@ -1210,7 +1262,8 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
     T* __restrict__ zv, T* __restrict__ p0, T* __restrict__ p1, T* __restrict__ xi, int mode,
     const RhsState* __restrict__ st, double* __restrict__ part) {
     constexpr int NQ = 4 * R + 2;
-    __shared__ __align__(16) char smem[ResidualSmem<V, R, BY, VX, YM>::bytes];
+    constexpr bool SHX = std::is_same<TS, BrickTiles>::value;  // bricks: shell cache
+    __shared__ __align__(16) char smem[ResidualSmem<V, R, BY, VX, YM, SHX>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -1218,7 +1271,7 @@ __global__ __launch_bounds__(64 * BY) void k_residual(
         double acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-        if (!residual_tile<V, T, R, BY, VX, YM, T4>(smem, bt, volp, labp, wc, sh, lab0, x64, rhs,
+        if (!residual_tile<V, T, R, BY, VX, YM, T4, SHX>(smem, bt, volp, labp, wc, sh, lab0, x64, rhs,
                                                     zv, p0, p1, xi, mode, st, acc))
             continue;
         block_sum_store<NQ, BY>(acc, part + bt.pidx, ts.ntiles);

@@ -106,11 +106,20 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     own float64 coarse solution (labels 2 and 3; label 1 as their
     complement), brick solves by the C oracle.  Both sides stop at relative
     residual 1e-8, so the comparison is not limited by the stopping rule."""
+    import sys
+    import time
+
     import torch
     from oracle import c_oracle, rw_oracle as O
+    t0 = time.perf_counter()
+
+    def say(msg):  # progress past pytest's capture: the oracle's part is long
+        print(f"hier1024 oracle test, {time.perf_counter() - t0:.0f} s: {msg}", file=sys.__stderr__,
+              flush=True)
     tol = 1e-8
     c = blob_case(shape=(1024, 1024, 1024), n_blobs=64, K=3, seeds_per_label=8000, sigma=0.08,
                   bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3, dtype="u16")
+    say("volume generated; GPU hierarchical solve")
     brick, offset = (64, 64, 64), (48, 20, 40)
     prob, info = rw.hierarchical_solve(dev(c.vol), dev(c.labels), 3, c.beta, levels=2,
                                        brick=brick, offset=offset, tol=tol,
@@ -118,6 +127,7 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
                                        level_dtype=torch.float32, return_info=True)
     act = [b for b, a in zip(info["bricks"], info["active"]) if a]
     its = [max(i) for i in info["brick_iters"]]
+    say(f"GPU done: {len(act)} active bricks, iterations {min(its)}..{max(its)}")
     assert len(act) == len(its) > 1000
     order = np.argsort(its)
     clipped = [i for i, (o, s) in enumerate(act) if min(s) < 64]
@@ -131,11 +141,17 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     del prob
     torch.cuda.empty_cache()
     # the oracle's own levels and coarse solution (float64)
+    say("oracle levels")
     g = O.case_g(c)
     g2, l2 = O.downsample_mean(O.downsample_mean(g)), O.coarse_seeds(O.coarse_seeds(c.labels))
-    coarse = np.stack([c_oracle.solve_box(g2, l2, s, c.beta, tol=tol)[0] for s in (2, 3)])
+    coarse = []
+    for lab in (2, 3):
+        say(f"oracle coarse solve of label {lab}")
+        coarse.append(c_oracle.solve_box(g2, l2, lab, c.beta, tol=tol)[0])
+    coarse = np.stack(coarse)
     for i in pick:
         o, s = (tuple(v) for v in act[i])
+        say(f"oracle brick {o} {s}")
         # upsampled coarse values over the brick and its one-voxel frame
         # (frame voxels outside the volume are ignored by the solve)
         frame = np.stack([O.upsample_trilinear(coarse[k], c.shape, 4,

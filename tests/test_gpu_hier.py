@@ -110,6 +110,40 @@ def test_brick_solves_match_oracle(rw, case, coarse_ref, precision):
                 assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
 
 
+@pytest.mark.parametrize("vx", [1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deep_brick_tiles_match_oracle(rw, case, coarse_ref, monkeypatch, precision, vx):
+    """Bricks 40 and 45 planes deep on 64-plane tiles: the residual's cache of
+    interpolated x-halo shell values is refilled within a tile (every 32
+    planes), and the solves still meet the oracle's (float64: the same
+    iteration counts to within one)."""
+    g, _, _, coarse = coarse_ref
+    monkeypatch.setenv("RW_BRICK_BY", "8")
+    monkeypatch.setenv("RW_BRICK_VX", str(vx))
+    monkeypatch.setenv("RW_BRICK_ZC", "64")
+    cands, active = rw.classify_bricks(dev(coarse), dev(case.labels), 4, (48, 48, 48), (5, 3, 7))
+    act = [b for b, a in zip(cands, active) if a and b[1][0] > 32][:4]
+    assert act
+    prob, iters, st = rw.solve_bricks(dev(case.vol), dev(case.labels), 3, case.beta, dev(coarse), 4,
+                                      act, tol=1e-8, precision=precision, return_stats=True)
+    assert st["status"] == 0 and st["tile"]["zc"] == 64
+    P = host(prob)
+    for (o, s), it in zip(act, iters):
+        o, s = tuple(o), tuple(s)
+        Pf = _up(coarse, case.shape, 4, tuple(np.array(o) - 1), tuple(np.array(s) + 2))
+
+        def shell_value(lab, zz, yy, xx, Pf=Pf, o=o):
+            return Pf[lab - 1][zz - o[0] + 1, yy - o[1] + 1, xx - o[2] + 1]
+
+        xb, info = O.solve_brick(g, case.labels, o, s, shell_value, Pf[:, 1:-1, 1:-1, 1:-1],
+                                 case.beta, tol=1e-8)
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        assert_parity(P[:, sl[0], sl[1], sl[2]], xb, what=f"deep brick {o} {s} {precision}")
+        if precision == "fp64":
+            for r in range(2):
+                assert abs(it[r] - info[r + 1]["iters"]) <= 1, (it, info)
+
+
 @pytest.mark.parametrize("by,zc,xcd,vx", [(4, 16, 0, 1), (8, 64, 0, 1), (16, 8, 1, 1),
                                           (8, 5, 1, 1), (4, 64, 0, 2), (8, 6, 1, 2)])
 def test_brick_tile_shapes_match_oracle(rw, case, coarse_ref, monkeypatch, by, zc, xcd, vx):
