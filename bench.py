@@ -221,8 +221,8 @@ def main():
                     help="blob512: timed steps of the hier1024 sub-object")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--nt", type=int, default=20,
-                    help="heart4d: time steps of the 50x224x224 series (the paper has 200; "
-                         "at one level those need more than 20000 CG iterations)")
+                    help="heart4d: time steps of the 50x224x224 series (the paper has 200: "
+                         "about 10000 mixed CG iterations, a minute per solve)")
     ap.add_argument("--pool", type=int, default=256,
                     help="stream2048: bricks per device pool")
     ap.add_argument("--update-delta", type=float, default=None,
@@ -633,7 +633,7 @@ def cpu_baseline_4d(case, gpu_iters, n_iter, threads, nt_sample=2):
 def bench_4d(args):
     """4-D random walker (Sec. V-B): a synthetic stand-in for the paper's
     cardiac MRI series, 50x224x224 voxels per time step and --nt time steps
-    (200 as in the paper), an ellipsoid pulsing over time on a noisy
+    (the paper has 200; 20 by default), an ellipsoid pulsing over time on a noisy
     background, 10 foreground and 10 background seeds in the first time step
     and 4 foreground seeds in the last, as in the paper's experiment.  One
     step = one whole-series solve (min-max reduction + rw_solve4d, mixed
