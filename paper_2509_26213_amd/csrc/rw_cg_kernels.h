@@ -340,9 +340,11 @@ __device__ __forceinline__ bool has_zp(const Geom& G, int gz) {
     return gz + 1 < G.nz && (!T4 || (gz + 1) % G.tz != 0);
 }
 
-// The five edge weights of a voxel in plane k, column v of the LDS tile
-// (-x, +x, -y, +y from LDS, +z from the registers), zero across the volume
-// border; d adds the -z weight carried from the previous plane.  T4 (volume
+// The five edge weights of a voxel in plane k, column v of the LDS tile:
+// -x, +x, -y, +y read from the batch's edge-weight planes (each in-plane
+// edge evaluated once, by the cell on its low side: publish_edge_weights),
+// +z from the registers, zero across the volume border; d adds the -z
+// weight carried from the previous plane.  T4 (volume
 // time series): eval_t adds the two time edges (the same voxel in the
 // previous and next time step, tz planes away) to d.
 template <typename T, typename Lanes, int U, bool T4 = false>
@@ -350,14 +352,24 @@ struct Stencil {
     using Tile = T[U][Lanes::TR + 2][Lanes::TC + 2];
     T wxm, wxp, wym, wyp, wzp, d;
     T wtm, wtp;
-    __device__ __forceinline__ void eval(const Tile& sg, int k, int v, const Lanes& L,
-                                         const Geom& G, int gz, T gc, T gzn, T wzm,
-                                         const WCoef& wc) {
+    // SW: the in-plane weights from the edge-weight planes swx / swy
+    // (publish_edge_weights), else evaluated here from the intensity plane sg
+    template <bool SW>
+    __device__ __forceinline__ void eval(const Tile& sg, const Tile& swx, const Tile& swy, int k,
+                                         int v, const Lanes& L, const Geom& G, int gz, T gc,
+                                         T gzn, T wzm, const WCoef& wc) {
         const int r = L.lr[v], c = L.lc[v];
-        wxm = L.gx[v] > 0 ? Weight<T>::of(gc - sg[k][r][c - 1], wc) : T(0);
-        wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][r][c + 1], wc) : T(0);
-        wym = L.gy[v] > 0 ? Weight<T>::of(gc - sg[k][r - 1][c], wc) : T(0);
-        wyp = L.gy[v] + 1 < G.ny ? Weight<T>::of(gc - sg[k][r + 1][c], wc) : T(0);
+        if constexpr (SW) {
+            wxm = L.gx[v] > 0 ? swx[k][r][c - 1] : T(0);
+            wxp = swx[k][r][c];
+            wym = L.gy[v] > 0 ? swy[k][r - 1][c] : T(0);
+            wyp = swy[k][r][c];
+        } else {
+            wxm = L.gx[v] > 0 ? Weight<T>::of(gc - sg[k][r][c - 1], wc) : T(0);
+            wxp = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][r][c + 1], wc) : T(0);
+            wym = L.gy[v] > 0 ? Weight<T>::of(gc - sg[k][r - 1][c], wc) : T(0);
+            wyp = L.gy[v] + 1 < G.ny ? Weight<T>::of(gc - sg[k][r + 1][c], wc) : T(0);
+        }
         wzp = has_zp<T4>(G, gz) ? Weight<T>::of(gc - gzn, wc) : T(0);
         d = wxm + wxp + wym + wyp + wzm + wzp;
     }
@@ -382,23 +394,69 @@ struct Stencil {
     }
 };
 
+// The +x and +y edge weights of a batch's cells into the edge-weight planes
+// (swx, swy: same layout as the intensity planes sg): every own cell
+// evaluates the edges to its +x and +y neighbours, the x-halo lanes of the
+// low side the edge from the left halo cell into the tile, and the lanes of
+// the top y-halo row the edges from that row into the tile.  A cell then
+// reads its -x / -y weight where its neighbour wrote the +x / +y one: three
+// exponentials per cell instead of five, the same values (an edge's weight
+// depends on the squared difference only).  Zero across the volume border
+// on the high side, as the cells' own tests give on the low side.  Called
+// between the barrier after the planes are published and another barrier.
+template <typename T, typename Lanes, int U, int VX>
+__device__ __forceinline__ void publish_edge_weights(T (&swx)[U][Lanes::TR + 2][Lanes::TC + 2],
+                                                     T (&swy)[U][Lanes::TR + 2][Lanes::TC + 2],
+                                                     const T (&sg)[U][Lanes::TR + 2][Lanes::TC + 2],
+                                                     const Lanes& L, const Geom& G,
+                                                     const T (&Gv)[U + 2][VX], const WCoef& wc) {
+    constexpr int NYH = Lanes::NYH;
+    constexpr int HV = Lanes::HV;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const int r = L.lr[v], c = L.lc[v];
+            const T gc = Gv[k + 1][v];
+            swx[k][r][c] = L.gx[v] + 1 < G.nx ? Weight<T>::of(gc - sg[k][r][c + 1], wc) : T(0);
+            swy[k][r][c] = L.gy[v] + 1 < G.ny ? Weight<T>::of(gc - sg[k][r + 1][c], wc) : T(0);
+        }
+    }
+    if (L.hx_use && L.hx_col_lds == 0) {
+        const int k = L.hx_k, r = L.hx_row_lds;
+        swx[k][r][0] = Weight<T>::of(sg[k][r][0] - sg[k][r][1], wc);
+    }
+#pragma unroll
+    for (int j = 0; j < NYH; ++j) {
+        if (L.hy_use[j] && L.hy_row_lds[j] == 0) {
+#pragma unroll
+            for (int h = 0; h < HV; ++h) {
+                const int k = L.hy_k[j], c = 64 * h + L.lx + 1;
+                swy[k][0][c] = Weight<T>::of(sg[k][0][c] - sg[k][1][c], wc);
+            }
+        }
+    }
+}
+
 // Pass 1: p_new = z + beta p_old (formed on the fly for the voxel and its
 // neighbours; zero on seeds and outside the box), q = A p_new, partial
 // p_new.q per label.  Label r reads p_old from buffer st.pcur of pb0/pb1 and
 // writes p_new to the other one.  qout (optional) receives q.  T4: a volume
 // time series (whole volume only); the two time neighbours of each own cell
 // are read directly, tz planes away.
-template <typename T, int R, int BY, int U, int VX, bool YM>
+template <typename T, int R, int BY, int U, int VX, bool YM, bool SW = false>
 struct PassSmem {
     using Lanes = TileLanes<BY, U, VX, YM>;
     static constexpr size_t plane = size_t(U) * (Lanes::TR + 2) * (Lanes::TC + 2);
-    static constexpr size_t bytes = sizeof(T) * plane * (1 + R);
+    // intensity, p per label, and (SW) the +x / +y edge weights
+    static constexpr size_t bytes = sizeof(T) * plane * (1 + R + (SW ? 2 : 0));
 };
 
 // One tile of pass 1, accumulated into acc (per label p_new.q); false if no
 // label of the tile's box iterates (uniform over the block).  smem: at least
 // PassSmem<T, R, BY, U, VX, YM>::bytes of LDS.
-template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false>
+template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false,
+          bool SW = false>
 __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const BoxTile& bt,
                                               const V* __restrict__ volp, WCoef wc,
                                               const T* __restrict__ zv, T* __restrict__ pb0,
@@ -411,6 +469,9 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
     using Plane = T[U][Lanes::TR + 2][Lanes::TC + 2];
     Plane& sg = *reinterpret_cast<Plane*>(smem);
     Plane(&sp)[R] = *reinterpret_cast<Plane(*)[R]>(smem + sizeof(Plane));
+    // the edge-weight planes exist with SW only (else they alias sg, unread)
+    Plane& swx = *reinterpret_cast<Plane*>(smem + (SW ? (1 + R) * sizeof(Plane) : 0));
+    Plane& swy = *reinterpret_cast<Plane*>(smem + (SW ? (2 + R) * sizeof(Plane) : 0));
     bool act[R];
     int src[R];
     if (box_labels<R>(st, bt.sidx, act, src) < 0) return false;  // uniform over the block
@@ -569,6 +630,10 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
                 Pv[U + 1][r][v] =
                     nin[U - 1] ? zN[U - 1][r][v] + bet[r] * oN[U - 1][r][v] : T(0);
         __syncthreads();
+        if constexpr (SW) {
+            publish_edge_weights<T, Lanes, U, VX>(swx, swy, sg, L, G, Gv, wc);
+            __syncthreads();
+        }
         // (4) stencil on planes zb..zb+U-1
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -581,7 +646,8 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
                 Stencil<T, Lanes, U, T4> S;
-                S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                S.template eval<SW>(sg, swx, swy, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v],
+                                    wzm[v], wc);
                 if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
                 const bool valid = L.in_box[v] && zin;
 #pragma unroll
@@ -617,13 +683,32 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
     return true;
 }
 
+// The passes keep four waves per SIMD (at most 128 VGPRs): their loads of a
+// batch are in flight while other waves compute, and with fewer waves the
+// latency shows.
+// Minimum waves per SIMD the compiler keeps for a pass (1: no constraint).
+// 128 x 4 float32 whole-volume tiles of one or two labels otherwise land a
+// few VGPRs above 128, one wave per SIMD short of four (with the cap: about
+// 110, no spills).
+template <typename T, int R, int BY, int U, int VX, bool T4, bool SW>
+constexpr int pass_min_waves() {
+    return SW && sizeof(T) == 4 && BY == 4 && U * VX == 4 && VX <= 2 && (R == 1 || (R == 2 && !T4))
+               ? 4
+               : 1;
+}
+
 template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
           bool T4 = false>
-__global__ __launch_bounds__(64 * BY) void k_cg_pass1(
+__global__ __launch_bounds__(64 * BY) __attribute__((
+    amdgpu_waves_per_eu(pass_min_waves<T, R, BY, U, VX, T4, std::is_same<TS, WholeTiles>::value>()))) void k_cg_pass1(
     const V* __restrict__ volp, WCoef wc, TS ts, const T* __restrict__ zv,
     T* __restrict__ pb0, T* __restrict__ pb1, T* __restrict__ qout,
     const RhsState* __restrict__ st, double* __restrict__ part) {
-    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM>::bytes];
+    // whole volumes share each in-plane edge weight through LDS; brick
+    // tiles (more planes per batch, one column per lane) run faster
+    // evaluating all five per cell
+    constexpr bool SW = std::is_same<TS, WholeTiles>::value;
+    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM, SW>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -631,7 +716,7 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
-        if (!cg_pass1_tile<V, T, R, BY, U, VX, YM, T4>(smem, bt, volp, wc, zv, pb0, pb1, qout, st,
+        if (!cg_pass1_tile<V, T, R, BY, U, VX, YM, T4, SW>(smem, bt, volp, wc, zv, pb0, pb1, qout, st,
                                                        acc))
             continue;
         block_sum_store<R, BY>(acc, part + bt.pidx, ts.ntiles);
@@ -643,7 +728,8 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass1(
 // ([2R][ntiles]).  T4 as in pass 1.
 // One tile of pass 2, accumulated into acc (per label r.z, r.r); false if
 // no label of the tile's box iterates.  smem as for pass 1.
-template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false>
+template <typename V, typename T, int R, int BY, int U, int VX, bool YM = false, bool T4 = false,
+          bool SW = false>
 __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const BoxTile& bt,
                                               const V* __restrict__ volp,
                                               const uint8_t* __restrict__ labp, WCoef wc,
@@ -657,6 +743,9 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
     using Plane = T[U][Lanes::TR + 2][Lanes::TC + 2];
     Plane& sg = *reinterpret_cast<Plane*>(smem);
     Plane(&sp)[R] = *reinterpret_cast<Plane(*)[R]>(smem + sizeof(Plane));
+    // the edge-weight planes exist with SW only (else they alias sg, unread)
+    Plane& swx = *reinterpret_cast<Plane*>(smem + (SW ? (1 + R) * sizeof(Plane) : 0));
+    Plane& swy = *reinterpret_cast<Plane*>(smem + (SW ? (2 + R) * sizeof(Plane) : 0));
     bool act[R];
     int src[R];
     if (box_labels<R>(st, bt.sidx, act, src) < 0) return false;
@@ -794,6 +883,10 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
             }
         }
         __syncthreads();
+        if constexpr (SW) {
+            publish_edge_weights<T, Lanes, U, VX>(swx, swy, sg, L, G, Gv, wc);
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int lz = zb + k;
@@ -803,7 +896,8 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
                 Stencil<T, Lanes, U, T4> S;
-                S.eval(sg, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v], wzm[v], wc);
+                S.template eval<SW>(sg, swx, swy, k, v, L, G, gz, Gv[k + 1][v], Gv[k + 2][v],
+                                    wzm[v], wc);
                 if constexpr (T4) S.eval_t(G, gz, Gv[k + 1][v], Gtm[k][v], Gtp[k][v], wc);
                 const T dinv = T(1) / S.d;
                 const bool valid = L.in_box[v] && zin && Lv[k][v] == 0;
@@ -847,11 +941,16 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
 
 template <typename V, typename T, int R, int BY, int U, int VX, typename TS, bool YM = false,
           bool T4 = false>
-__global__ __launch_bounds__(64 * BY) void k_cg_pass2(
+__global__ __launch_bounds__(64 * BY) __attribute__((
+    amdgpu_waves_per_eu(pass_min_waves<T, R, BY, U, VX, T4, std::is_same<TS, WholeTiles>::value>()))) void k_cg_pass2(
     const V* __restrict__ volp, const uint8_t* __restrict__ labp, WCoef wc, TS ts,
     T* __restrict__ xv, T* __restrict__ zv, const T* __restrict__ pb0,
     const T* __restrict__ pb1, const RhsState* __restrict__ st, double* __restrict__ part) {
-    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM>::bytes];
+    // whole volumes share each in-plane edge weight through LDS; brick
+    // tiles (more planes per batch, one column per lane) run faster
+    // evaluating all five per cell
+    constexpr bool SW = std::is_same<TS, WholeTiles>::value;
+    __shared__ __align__(16) char smem[PassSmem<T, R, BY, U, VX, YM, SW>::bytes];
     const int cnt = ts.count();
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         BoxTile bt;
@@ -859,7 +958,7 @@ __global__ __launch_bounds__(64 * BY) void k_cg_pass2(
         double acc[2 * R];
 #pragma unroll
         for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
-        if (!cg_pass2_tile<V, T, R, BY, U, VX, YM, T4>(smem, bt, volp, labp, wc, xv, zv, pb0, pb1,
+        if (!cg_pass2_tile<V, T, R, BY, U, VX, YM, T4, SW>(smem, bt, volp, labp, wc, xv, zv, pb0, pb1,
                                                        st, acc))
             continue;
         block_sum_store<2 * R, BY>(acc, part + bt.pidx, ts.ntiles);
