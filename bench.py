@@ -187,7 +187,9 @@ def cpu_baseline_hier(case, coarse_iters, bricks, brick_iters, n_iter, threads, 
     per_vox_iter = []
     for i in pick:
         o, s = bricks[i]
-        shell = np.zeros(tuple(int(v) + 2 for v in s))
+        # Dirichlet data 0.5 on the shell: a nonzero right-hand side, so every
+        # sampled brick runs its n_iter iterations (a zero one stops at once)
+        shell = np.full(tuple(int(v) + 2 for v in s), 0.5)
         t0 = time.perf_counter()
         _, its, _, _ = c_oracle.solve_box(g, case.labels, 2, case.beta, tol=1e-300,
                                           max_iter=n_iter, box=(tuple(o), tuple(s)), shell=shell,
