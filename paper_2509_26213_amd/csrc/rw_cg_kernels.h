@@ -491,6 +491,20 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
     }
     Lanes L;
     L.init(G, bt);
+    // halo cells of the vectors outside the box read as zero: on brick tiles
+    // (not SW) a wave none of whose halo lanes lies in the box (the x-halo of
+    // a brick-wide tile, the y-halo at the brick's faces) issues none of
+    // those loads; whole-volume tiles load them (their halo is outside the
+    // box only at the volume border, and the test costs them registers)
+    const bool hx_vec = SW || __ballot(L.hx_box) != 0;
+    bool hy_vec[Lanes::NYH];
+#pragma unroll
+    for (int j = 0; j < Lanes::NYH; ++j) {
+        bool any = false;
+#pragma unroll
+        for (int h = 0; h < Lanes::HV; ++h) any = any || L.hy_box[j][h];
+        hy_vec[j] = SW || __ballot(any) != 0;
+    }
     const int64_t bplane = (int64_t)bt.sx * bt.sy;
 
     T Gv[U + 2][VX], Pv[U + 2][R][VX];  // own columns: planes z-1, z, z+1 .. z+U
@@ -565,8 +579,8 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
             hxg = (T)ldu(vol + o.v, L.hx_colv);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                hxz[r] = ldu(zr[r] + o.b, L.hx_colb);
-                hxo[r] = ldu(po[r] + o.b, L.hx_colb);
+                hxz[r] = hx_vec ? ldu(zr[r] + o.b, L.hx_colb) : T(0);
+                hxo[r] = hx_vec ? ldu(po[r] + o.b, L.hx_colb) : T(0);
             }
         }
         T hyg[NYH][HV], hyz[NYH][R][HV], hyo[NYH][R][HV];
@@ -578,8 +592,8 @@ __device__ __forceinline__ bool cg_pass1_tile(char* __restrict__ smem, const Box
                 hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    hyz[j][r][h] = ldu(zr[r] + o.b, L.hy_colb[j][h]);
-                    hyo[j][r][h] = ldu(po[r] + o.b, L.hy_colb[j][h]);
+                    hyz[j][r][h] = hy_vec[j] ? ldu(zr[r] + o.b, L.hy_colb[j][h]) : T(0);
+                    hyo[j][r][h] = hy_vec[j] ? ldu(po[r] + o.b, L.hy_colb[j][h]) : T(0);
                 }
             }
         }
@@ -766,6 +780,20 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
     }
     Lanes L;
     L.init(G, bt);
+    // halo cells of the vectors outside the box read as zero: on brick tiles
+    // (not SW) a wave none of whose halo lanes lies in the box (the x-halo of
+    // a brick-wide tile, the y-halo at the brick's faces) issues none of
+    // those loads; whole-volume tiles load them (their halo is outside the
+    // box only at the volume border, and the test costs them registers)
+    const bool hx_vec = SW || __ballot(L.hx_box) != 0;
+    bool hy_vec[Lanes::NYH];
+#pragma unroll
+    for (int j = 0; j < Lanes::NYH; ++j) {
+        bool any = false;
+#pragma unroll
+        for (int h = 0; h < Lanes::HV; ++h) any = any || L.hy_box[j][h];
+        hy_vec[j] = SW || __ballot(any) != 0;
+    }
 
     T Gv[U + 2][VX], Pv[U + 2][R][VX];
     {
@@ -839,7 +867,7 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
             const PlaneOff o = plane_off(G, bt, zb + L.hx_k);
             hxg = (T)ldu(vol + o.v, L.hx_colv);
 #pragma unroll
-            for (int r = 0; r < R; ++r) hxp[r] = ldu(pr[r] + o.b, L.hx_colb);
+            for (int r = 0; r < R; ++r) hxp[r] = hx_vec ? ldu(pr[r] + o.b, L.hx_colb) : T(0);
         }
         T hyg[NYH][HV], hyp[NYH][R][HV];
 #pragma unroll
@@ -849,7 +877,8 @@ __device__ __forceinline__ bool cg_pass2_tile(char* __restrict__ smem, const Box
             for (int h = 0; h < HV; ++h) {
                 hyg[j][h] = (T)ldu(vol + o.v, L.hy_colv[j][h]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) hyp[j][r][h] = ldu(pr[r] + o.b, L.hy_colb[j][h]);
+                for (int r = 0; r < R; ++r)
+                    hyp[j][r][h] = hy_vec[j] ? ldu(pr[r] + o.b, L.hy_colb[j][h]) : T(0);
             }
         }
         __syncthreads();
