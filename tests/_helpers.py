@@ -84,3 +84,16 @@ def c_brick_solver(g, labels, beta, tol, labels_solved):
             info.append(dict(label=s, iters=it, status=st))
         return np.stack(xs), info
     return solve
+
+
+def progress(request, msg):
+    """A progress line on the real terminal, past pytest's output capture
+    (long oracle computations otherwise run silent for minutes)."""
+    import sys
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    if capman is None:
+        print(msg, flush=True)
+        return
+    with capman.global_and_fixture_disabled():
+        sys.stdout.write(msg + "\n")
+        sys.stdout.flush()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from synth import blob_case, sphere_case
-from tests._helpers import assert_parity, dev, host
+from tests._helpers import assert_parity, dev, host, progress
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_sphere128_gradients_vs_central_differences(rw):
 
 
 @pytest.mark.timeout(900)
-def test_hier1024_sampled_bricks_vs_oracle(rw):
+def test_hier1024_sampled_bricks_vs_oracle(rw, request):
     """The full-size hierarchical workload (1024^3 uint16, 64 blobs, 8000
     seeds per label, K = 3, 64^3 bricks on the offset grid, the bench's tile
     shapes): six of the GPU's active bricks (lowest and highest GPU iteration
@@ -106,17 +106,16 @@ def test_hier1024_sampled_bricks_vs_oracle(rw):
     own float64 coarse solution (labels 2 and 3; label 1 as their
     complement), brick solves by the C oracle.  Both sides stop at relative
     residual 1e-8, so the comparison is not limited by the stopping rule."""
-    import sys
     import time
 
     import torch
     from oracle import c_oracle, rw_oracle as O
     t0 = time.perf_counter()
 
-    def say(msg):  # progress past pytest's capture: the oracle's part is long
-        print(f"hier1024 oracle test, {time.perf_counter() - t0:.0f} s: {msg}", file=sys.__stderr__,
-              flush=True)
+    def say(msg):  # progress on the terminal: the oracle's part is long
+        progress(request, f"hier1024 oracle test, {time.perf_counter() - t0:.0f} s: {msg}")
     tol = 1e-8
+    say("generating the 1024^3 volume")
     c = blob_case(shape=(1024, 1024, 1024), n_blobs=64, K=3, seeds_per_label=8000, sigma=0.08,
                   bg=0.2, rmin=10.0, rmax=60.0, beta=150.0, seed=3, dtype="u16")
     say("volume generated; GPU hierarchical solve")

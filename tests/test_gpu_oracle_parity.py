@@ -3,14 +3,12 @@ not reach: the whole-volume tile shape of the 512^3 benchmark on a 256^3 blob
 volume (both precisions, element by element); four labels (three solved
 ones) in whole-volume, brick and streamed solves; a forced CG breakdown; and
 the 128^3 adjoint gradient against the oracle's own float64 adjoint."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import rw_oracle as O
 from synth import blob_case, sphere_case
-from tests._helpers import assert_parity, c_brick_solver, dev, host, near_threshold
+from tests._helpers import assert_parity, c_brick_solver, dev, host, near_threshold, progress
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +28,7 @@ def rw():
 
 
 @pytest.fixture(scope="module")
-def blob256():
+def blob256(request):
     """The 512^3 benchmark generator at 256^3 with its density (4 blobs,
     125 seeds per label) and the oracle's float64 Jacobi-PCG solve of every
     label at tol 1e-10.  On this volume the stopping rule alone moves the
@@ -45,7 +43,7 @@ def blob256():
     g = O.case_g(c)
     ref, info = [], []
     for s in (1, 2, 3):  # one label at a time, progress past pytest's capture
-        print(f"blob256: oracle solve of label {s} at tol 1e-10", file=sys.__stderr__, flush=True)
+        progress(request, f"blob256: oracle solve of label {s} at tol 1e-10")
         x, i = c_oracle.random_walker(g, c.labels, 3, c.beta, tol=1e-10, solve_labels=[s],
                                       return_info=True)
         ref.append(x[0])
