@@ -1,6 +1,6 @@
 """The tile orders of the stencil kernels (plain and time series, plain and
 XCD-aware), checked on the host: tests/tilemap_check.hip includes the
-library's tile-map header, builds the maps for 2400 grid / tile shapes and
+library's tile-map header, builds the maps for 2880 grid / tile shapes and
 checks that block slots map one to one onto tiles that cover every plane of
 every column exactly once, time-series chunks never straddling a step."""
 import os
