@@ -18,8 +18,28 @@ int main() {
         G.nx = nx; G.ny = ny; G.nz = nt * nzs;
         G.plane = (int64_t)nx * ny; G.n = G.plane * G.nz;
         const int maxt = make_tilemap(G, 4, 4, 0).tiles;
+        // the plain volume order, both tile orders, two plane counts
+        for (int zc : {4, 32})
+        for (int xcd : {0, 1}) {
+            const TileMap p = make_tilemap(G, by, zc, xcd, vx);
+            std::vector<int> seen(p.tiles, 0);
+            std::vector<int> cover((size_t)G.nz * p.gx * p.gy, 0);
+            for (int b = 0; b < p.blocks(); ++b) {
+                const int t = p.tile(b);
+                if (t < 0) continue;
+                if (t >= p.tiles) { ++bad; continue; }
+                seen[t]++;
+                const int tx = t % p.gx, ty = (t / p.gx) % p.gy, tz = t / (p.gx * p.gy);
+                int z0, z1;
+                p.planes(tz, G.nz, z0, z1);
+                for (int z = z0; z < z1; ++z) cover[((size_t)z * p.gy + ty) * p.gx + tx]++;
+            }
+            for (int v : seen) if (v != 1) ++bad;
+            for (int v : cover) if (v != 1) ++bad;
+            ++cases;
+        }
         TileMap m;
-        if (!make_tilemap_series(G, by, vx, nt, nzs, maxt, m)) { printf("no series map nx %d ny %d nzs %d nt %d by %d vx %d\n", nx, ny, nzs, nt, by, vx); continue; }
+        if (!make_tilemap_series(G, by, vx, nt, nzs, maxt, m)) continue;
         ++cases;
         std::vector<int> seen(m.tiles, 0);
         std::vector<int> cover((size_t)G.nz * m.gx * m.gy, 0);
