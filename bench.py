@@ -246,7 +246,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU (a volume sharded over GPUs is not implemented); --gpus must be 1",
                           "n_gpus": args.gpus}))
         raise SystemExit(2)
 
